@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: matrix-free P1 apply on 288 jittered macro-tets at level 8.
+
+Workload: the 4x4x3 Kuhn box (288 macro-tetrahedra, interior macro-vertices
+jittered by U[-0.1, 0.1]^3, seed 3) refined to level 8: 802,687,743 interior
+DoFs.  One step = one FP64 operator application y = A x (cell stencil kernel
++ ghost exchange), inputs resident in HBM.  Also reported: per-kernel device
+time and HBM roofline of the dominant kernel, FP32 apply, time to a 1e-10
+relative residual for FP64 V(2,2) cycles and for FP32-in-FP64 iterative
+refinement, and the CPU oracle's assembled sparse apply timed on the host.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_DOF_F64 = 16.0   # read x, write y per interior DoF
+BYTES_PER_DOF_F32 = 8.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--level", type=int, default=8)
+    p.add_argument("--no-solve", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--cpu-level", type=int, default=5)
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def cpu_baseline(level: int, budget_s: float):
+    """The oracle's assembled CSR apply (SciPy, one thread) on the same mesh at
+    a level the host can assemble; GDoF/s over interior DoFs."""
+    import numpy as np
+    from oracle.fem import P1System
+    from oracle.refine import MicroMesh
+    from workloads import jittered_kuhn_box, uniform_values
+    t0 = time.time()
+    S = P1System(MicroMesh(*jittered_kuhn_box(4, 4, 3, 0.1, 3), level))
+    setup = time.time() - t0
+    x = uniform_values(S.mesh.num_vertices, 4)
+    x[S.dirichlet] = 0.0
+    S.apply(x)
+    reps, t1 = 0, time.time()
+    while True:
+        S.apply(x)
+        reps += 1
+        el = time.time() - t1
+        if el >= budget_s:
+            break
+    dofs = int(S.interior.sum())
+    return {"value": round(dofs * reps / el / 1e9, 6), "unit": "GDoF/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"288-cell jittered mesh at level {level} ({dofs} interior "
+                      f"DoFs, CSR nnz {S.A.nnz}), SciPy CSR apply, {reps} reps "
+                      f"in {el:.1f} s (assembly {setup:.1f} s untimed)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU "
+              "path (see DESIGN.md, 'Sharding'); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2308_01792_amd as ht
+    from workloads import jittered_kuhn_box
+
+    L = args.level
+    log(f"mesh setup (levels 2..{L})")
+    xyz, cells = jittered_kuhn_box(4, 4, 3, amplitude=0.1, seed=3)
+    mesh = ht.Mesh(xyz, cells, 2, L)
+    info = mesh.info(L)
+    ndof, nslot = info["n_dofs"], info["n_slots"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    gen = torch.Generator(device=dev).manual_seed(4)
+    x = torch.rand(nslot, dtype=torch.float64, device=dev, generator=gen) * 2 - 1
+    mesh.sync(L, x)
+    mesh.fill_dirichlet(L, x, 0.0)
+    y = torch.zeros_like(x)
+    torch.cuda.synchronize()
+
+    # ---------------- headline: FP64 apply -------------------------------
+    log(f"FP64 apply: {args.warmup} warmup + {args.steps} timed steps, "
+        f"{ndof} DoFs")
+    for _ in range(args.warmup):
+        mesh.apply(L, x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        mesh.apply(L, x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    gdofs = ndof / (ms * 1e-3) / 1e9
+    log(f"apply: {ms:.3f} ms/step, {gdofs:.1f} GDoF/s")
+
+    # per-kernel device time (HIP events around every library launch, on
+    # the launch stream)
+    mesh.profile(True)
+    mesh.profile_reset()
+    for _ in range(args.steps):
+        mesh.apply(L, x, y)
+    torch.cuda.synchronize()
+    cell_ms, ncell = mesh.profile_query("cell_apply")
+    exch_ms, nexch = mesh.profile_query("exchange")
+    mesh.profile(False)
+    cell_avg, exch_avg = cell_ms / ncell, exch_ms / nexch
+    achieved = BYTES_PER_DOF_F64 * ndof / (cell_avg * 1e-3) / 1e9
+    log(f"cell kernel {cell_avg:.3f} ms ({achieved:.0f} GB/s algorithmic), "
+        f"exchange {exch_avg:.3f} ms")
+
+    # ---------------- FP32 apply ------------------------------------------
+    x32, y32 = x.float(), torch.zeros(nslot, dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        mesh.apply(L, x32, y32)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        mesh.apply(L, x32, y32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1) / args.steps
+    del x32, y32
+
+    out = {
+        "metric": "GDoF/s of matrix-free P1 apply + %HBM roofline; V-cycle "
+                  "time to 1e-10 FP32/FP64",
+        "value": round(gdofs, 3),
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"288 jittered macro-tets (4x4x3 Kuhn box, "
+                               f"seed 3) at level {L}, FP64 apply",
+                   "level": L, "macro_cells": 288, "dofs": ndof,
+                   "slots": nslot},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "kernel": "k_cell<double, apply>",
+                     "bytes_per_launch": BYTES_PER_DOF_F64 * ndof},
+        "apply_hbm_frac": round(gdofs * BYTES_PER_DOF_F64 / HBM_PEAK_GBS, 4),
+        "kernel_ms": {"cell_apply": round(cell_avg, 4),
+                      "exchange": round(exch_avg, 4)},
+        "apply_f32": {"ms": round(ms32, 4),
+                      "gdofs": round(ndof / (ms32 * 1e-3) / 1e9, 3),
+                      "hbm_frac": round(ndof * BYTES_PER_DOF_F32 / (ms32 * 1e-3)
+                                        / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+
+    # ---------------- solves to 1e-10 --------------------------------------
+    if not args.no_solve:
+        del y
+        m = torch.zeros_like(x)
+        mesh.lumped_mass(L, m)
+        f = torch.rand(nslot, dtype=torch.float64, device=dev,
+                       generator=torch.Generator(device=dev).manual_seed(5)) * 2 - 1
+        mesh.sync(L, f)
+        b = m * f
+        del m, f, x
+        solves = {}
+        for name, prec in (("f64", ht.HT_PREC_F64), ("mixed", ht.HT_PREC_MIXED)):
+            u = torch.zeros_like(b)
+            mesh.solve(L, u, b, prec, 1e-10, 100, use_graph=True)   # warm-up
+            u.zero_()
+            torch.cuda.synchronize()
+            st = mesh.solve(L, u, b, prec, 1e-10, 100, use_graph=True)
+            solves[name] = {"seconds": round(st["seconds"], 4),
+                            "cycles": st["cycles"],
+                            "rel_res": st["rel_res"]}
+            if name == "f64":
+                u64 = u
+            else:
+                diff = u - u64
+                solves[name]["rel_diff_vs_f64"] = mesh.norm(L, diff) / mesh.norm(L, u64)
+            log(f"solve {name}: {st['cycles']} cycles, {st['seconds']:.3f} s, "
+                f"rel res {st['rel_res']:.2e}")
+        out["solve_to_1e-10"] = solves
+
+    if not args.no_cpu:
+        log(f"CPU oracle baseline at level {args.cpu_level}")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_level, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

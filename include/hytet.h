@@ -1,0 +1,218 @@
+/* hytet -- matrix-free P1 finite elements on regularly refined macro-tetrahedra,
+ * for AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The library implements the hot path of Kohl, Bauer, Boehm, Ruede,
+ * "Fundamental data structures for matrix-free finite elements on hybrid
+ * tetrahedral grids" (arXiv:2308.01792):
+ *   - a coarse tetrahedral mesh is turned into a graph of macro-primitives
+ *     (cells, faces, edges, vertices; Section 2),
+ *   - every macro-cell is refined regularly with the rule of eq. (bey)
+ *     (Section 3.1); micro-vertices are addressed by index functions over
+ *     tetrahedral polytopes (Section 4),
+ *   - the P1 Laplacian a_ij = sum_T int_T grad phi_i . grad phi_j
+ *     (Section 5.2.1) is applied matrix-free as a 15-point stencil whose
+ *     weights are precomputed once per macro-cell from its geometry,
+ *     independent of the level (Section 5.2.3, constant coefficients),
+ *   - vectors live on a range of levels and every call names its level
+ *     (Section 5.1), which makes geometric multigrid (weighted Jacobi,
+ *     restriction, prolongation, V-cycle, iterative refinement) direct.
+ *
+ * Conventions
+ *   Vectors.  A level-l vector is a caller-owned device array of n_slots
+ *     elements (ht_mesh_query) of type double (HT_F64) or float (HT_F32),
+ *     256-byte aligned.  Slot s holds one copy of one micro-vertex value.
+ *     Micro-vertices shared by several macro-cells (on macro-faces, -edges,
+ *     -vertices) have one copy per incident cell; exactly one copy is the
+ *     owner.  A vector is *consistent* when all copies of every micro-vertex
+ *     are equal; inputs must be consistent (ht_sync makes them so) and every
+ *     output is consistent.  Padding slots (flag HT_SLOT_PAD) are never read
+ *     nor written.
+ *   Boundary.  Micro-vertices on macro-faces with a single incident cell are
+ *     Dirichlet vertices.  Their input values are boundary data; outputs of
+ *     apply/residual/restrict hold 0 there, smoothers and solvers leave them
+ *     unchanged.
+ *   Keys.  A micro-vertex is identified, independently of the layout, by its
+ *     key: the (global macro-vertex id, integer barycentric weight) pairs with
+ *     non-zero weight, ascending by id, padded with (-1, 0) to four pairs;
+ *     weights sum to 2^level.  Two slots hold the same micro-vertex iff their
+ *     keys are equal.
+ *   Streams.  ht_stream is a hipStream_t (0 = null stream).  Device calls are
+ *     asynchronous on it unless stated otherwise.
+ *   Errors.  Every call returns an HT_* status; ht_last_error() describes the
+ *     last failure of the calling thread.  Nothing throws or aborts across
+ *     the ABI.  A mesh is not thread-safe.
+ */
+#ifndef HYTET_H
+#define HYTET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ht_mesh ht_mesh;
+typedef struct ht_batch ht_batch;
+typedef void* ht_stream; /* hipStream_t */
+
+enum {
+  HT_OK = 0,
+  HT_ERR_ARG = 1,            /* null/misaligned pointer, bad option value */
+  HT_ERR_MESH = 2,           /* degenerate, duplicated or non-conforming */
+  HT_ERR_LEVEL = 3,          /* level outside the mesh's level range */
+  HT_ERR_OOM = 4,            /* device allocation failed */
+  HT_ERR_HIP = 5,            /* a HIP runtime call failed */
+  HT_ERR_NOT_CONVERGED = 6,  /* solver hit max_cycles or diverged */
+  HT_ERR_STATE = 7           /* no GPU / call not valid in this state */
+};
+enum { HT_F64 = 0, HT_F32 = 1 };
+enum { HT_PREC_F64 = 0, HT_PREC_MIXED = 1 };
+enum {
+  HT_SLOT_OWNER = 1,     /* the owning copy of its micro-vertex */
+  HT_SLOT_GHOST = 2,     /* a further copy of a shared micro-vertex */
+  HT_SLOT_DIRICHLET = 4, /* micro-vertex on the domain boundary */
+  HT_SLOT_PAD = 8        /* padding, holds no micro-vertex */
+};
+
+typedef struct {
+  int64_t n_slots;     /* vector length at this level */
+  int64_t n_dofs;      /* unique non-Dirichlet micro-vertices (unknowns) */
+  int64_t n_unique;    /* unique micro-vertices, boundary included */
+  int64_t n_cells, n_faces, n_edges, n_vertices; /* macro-primitives */
+  int64_t cell_stride; /* slots per macro-cell block */
+} ht_level_info;
+
+typedef struct {
+  int nu1, nu2;        /* pre- and post-smoothing sweeps */
+  double omega;        /* Jacobi weight, e.g. 2/3 */
+  int coarse_level;    /* level solved exactly (dense Cholesky inverse) */
+} ht_cycle_opts;
+
+typedef struct {
+  ht_cycle_opts cyc;
+  int precision;       /* HT_PREC_F64 or HT_PREC_MIXED */
+  double rel_tol;      /* stop when ||b - A u||_2 <= rel_tol ||b||_2 */
+  int max_cycles;      /* <= 256 */
+  int use_graph;       /* replay each cycle as a captured hipGraph */
+} ht_solve_opts;
+
+typedef struct {
+  int cycles;          /* V-cycles (or refinement steps) performed */
+  int converged;
+  double rel_res;      /* final relative residual (FP64) */
+  double seconds;      /* wall time of the solve */
+  double res_history[257]; /* relative residual before cycle 0, 1, ... */
+} ht_solve_stats;
+
+/* ------------------------------------------------------------ general -- */
+const char* ht_last_error(void);
+int ht_version(void);
+/* t_w(i,j,k) of the paper's linearisation of I_tet(w) (Section 4). */
+int64_t ht_index_tw(int64_t w, int64_t i, int64_t j, int64_t k);
+
+/* --------------------------------------------------------------- mesh -- */
+/* Build the macro-primitive graph (Section 2) of a conforming tetrahedral
+ * mesh and the per-cell stencils of every level in [min_level, max_level].
+ * xyz: host [nv][3] doubles; cells: host [nc][4] global vertex ids.  The
+ * local vertex order of each cell is kept: it selects the inner diagonal of
+ * the regular refinement (Section 3.1).  Both arrays are copied.  Host-only:
+ * device memory is allocated on the first device call.
+ * HT_ERR_MESH for a degenerate cell, repeated vertex, a face shared by more
+ * than two cells or an out-of-range id; HT_ERR_LEVEL if the levels are not
+ * 0 <= min_level <= max_level <= 10. */
+int ht_mesh_create(const double* xyz, int64_t nv, const int64_t* cells,
+                   int64_t nc, int min_level, int max_level, ht_mesh** out);
+int ht_mesh_destroy(ht_mesh* mesh);
+int ht_mesh_query(const ht_mesh* mesh, int level, ht_level_info* info);
+
+/* Keys (int64[count][8]) and/or flags (HT_SLOT_*) of slots
+ * [first, first + count) at a level; either output may be NULL.  Host. */
+int ht_vertex_keys(const ht_mesh* mesh, int level, int64_t first,
+                   int64_t count, int64_t* keys, uint8_t* flags);
+/* Coordinates (double[count][3]) of slots [first, first+count).  Host.
+ * A micro-vertex with key pairs (g_m, w_m) sits at sum_m w_m X_{g_m} / 2^l. */
+int ht_vertex_coords(const ht_mesh* mesh, int level, int64_t first,
+                     int64_t count, double* xyz);
+/* Same for all slots into device memory xyz_dev[n_slots][3] of dtype. */
+int ht_vertex_coords_device(ht_mesh* mesh, int level, int dtype,
+                            void* xyz_dev, ht_stream stream);
+/* Slot flags for all slots into device memory (uint8[n_slots]). */
+int ht_slot_flags_device(ht_mesh* mesh, int level, uint8_t* flags_dev,
+                         ht_stream stream);
+/* Slot of local index (i,j,k), i+j+k <= 2^level, of macro-cell `cell`. */
+int ht_slot_index(const ht_mesh* mesh, int level, int64_t cell, int i, int j,
+                  int k, int64_t* slot);
+/* Class-partial stencils of every cell at a level: out[nc][16][15] doubles.
+ * Class c (bits: i==0, j==0, k==0, i+j+k==n) entry d is the sum of the
+ * element-matrix entries of the cell's micro-tets around a point of class c
+ * that connect it to offset d (offset order in the documentation). */
+int ht_cell_stencils(const ht_mesh* mesh, int level, double* out);
+
+/* ------------------------------------------------------- vector ops ---- */
+/* Make a vector consistent: every copy takes its owner's value. */
+int ht_sync(ht_mesh* mesh, int level, int dtype, void* v, ht_stream stream);
+/* Set all Dirichlet slots to `value` (all copies). */
+int ht_fill_dirichlet(ht_mesh* mesh, int level, int dtype, void* v,
+                      double value, ht_stream stream);
+/* Lumped P1 mass m_i = sum_{T contains i} |T|/4 at every slot. */
+int ht_lumped_mass(ht_mesh* mesh, int level, int dtype, void* m,
+                   ht_stream stream);
+/* Euclidean norm over unique non-Dirichlet micro-vertices (synchronises). */
+int ht_norm(ht_mesh* mesh, int level, int dtype, const void* v, double* norm,
+            ht_stream stream);
+/* Dot product over unique non-Dirichlet micro-vertices (synchronises). */
+int ht_dot(ht_mesh* mesh, int level, int dtype, const void* a, const void* b,
+           double* dot, ht_stream stream);
+
+/* ------------------------------------------------------------ operators - */
+/* y = A x: the P1 Laplacian row sum_j a_ij x_j at every non-Dirichlet
+ * micro-vertex (Section 5.2.2), y = 0 at Dirichlet ones.  x and y must not
+ * alias. */
+int ht_apply(ht_mesh* mesh, int level, int dtype, const void* x, void* y,
+             ht_stream stream);
+/* r = b - A u (0 at Dirichlet); if norm != NULL, also ||r||_2 over unique
+ * non-Dirichlet micro-vertices (synchronises the stream). */
+int ht_residual(ht_mesh* mesh, int level, int dtype, const void* u,
+                const void* b, void* r, double* norm, ht_stream stream);
+/* `sweeps` weighted Jacobi sweeps u <- u + omega D^-1 (b - A u). */
+int ht_smooth_jacobi(ht_mesh* mesh, int level, int dtype, double omega,
+                     int sweeps, void* u, const void* b, ht_stream stream);
+/* r_coarse = P^T r_fine (Dirichlet entries of r_fine taken as zero, coarse
+ * Dirichlet entries set to zero); P = nested P1 interpolation. */
+int ht_restrict(ht_mesh* mesh, int fine_level, int dtype, const void* r_fine,
+                void* r_coarse, ht_stream stream);
+/* u_fine += P e_coarse (Dirichlet entries of e_coarse taken as zero). */
+int ht_prolongate_add(ht_mesh* mesh, int coarse_level, int dtype,
+                      const void* e_coarse, void* u_fine, ht_stream stream);
+/* Exact solve of the interior equations at `level` (dense Cholesky inverse
+ * computed on the host at first use), Dirichlet values of u kept. */
+int ht_coarse_solve(ht_mesh* mesh, int level, int dtype, const void* b,
+                    void* u, ht_stream stream);
+/* One V(nu1, nu2) cycle for A u = b at `level` down to opts->coarse_level. */
+int ht_vcycle(ht_mesh* mesh, int level, int dtype, const ht_cycle_opts* opts,
+              void* u, const void* b, ht_stream stream);
+/* Solve A u = b (u, b: HT_F64 vectors) from the given u.  HT_PREC_F64 runs
+ * FP64 V-cycles; HT_PREC_MIXED runs FP32 V-cycles inside FP64 iterative
+ * refinement (FP64 residual, FP64 update, FP64 coarse solve).  Synchronises
+ * once per cycle to read the residual norm. */
+int ht_solve(ht_mesh* mesh, int level, const ht_solve_opts* opts, void* u,
+             const void* b, ht_solve_stats* stats, ht_stream stream);
+
+/* ---------------------------------------------------------- profiling -- */
+/* Record HIP events around every kernel the library launches. */
+int ht_profile_enable(ht_mesh* mesh, int enable);
+/* Summed device milliseconds and launch count of kernels whose name starts
+ * with `prefix` since the last reset (synchronises). */
+int ht_profile_query(ht_mesh* mesh, const char* prefix, double* ms,
+                     int64_t* launches);
+int ht_profile_reset(ht_mesh* mesh);
+
+/* Diagnostics: runs a one-wave kernel that checks the cross-lane shifts the
+ * stencil kernel relies on; *mismatches = number of wrong lanes (0 = OK). */
+int ht_selftest_lane_shift(int* mismatches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYTET_H */

@@ -190,10 +190,13 @@ class MicroMesh:
         """Vertex indices of the given keys (every key must exist)."""
         keys = np.asarray(keys, dtype=np.int64)
         if self._codec is not None:
-            c = self._codec[0](keys)
+            c = np.asarray(self._codec[0](keys))
+            shape = c.shape
+            c = c.reshape(-1)
             idx = np.searchsorted(self.codes, c)
             ok = (idx < len(self.codes))
             ok[ok] = self.codes[idx[ok]] == c[ok]
+            idx, ok = idx.reshape(shape), ok.reshape(shape)
         else:
             flat = keys.reshape(-1, 8)
             table = {tuple(r): i for i, r in enumerate(self.keys)}

@@ -1,0 +1,235 @@
+"""Python binding of libhytet (matrix-free P1 on refined macro-tetrahedra).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+``libhytet.so`` (C ABI in ``include/hytet.h``).  PyTorch provides device
+memory and streams; vectors are 1-D CUDA tensors of ``n_slots`` elements
+(float64 or float32) in the library's closure layout.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (HT_F32, HT_F64, HT_PREC_F64, HT_PREC_MIXED,
+                   HT_SLOT_DIRICHLET, HT_SLOT_GHOST, HT_SLOT_OWNER,
+                   HT_SLOT_PAD, HytetError, check)
+
+__all__ = ["Mesh", "HytetError", "load", "HT_F64", "HT_F32", "HT_PREC_F64",
+           "HT_PREC_MIXED", "HT_SLOT_OWNER", "HT_SLOT_GHOST",
+           "HT_SLOT_DIRICHLET", "HT_SLOT_PAD", "index_tw",
+           "selftest_lane_shift"]
+
+
+def load():
+    return _lib.load()
+
+
+def index_tw(w: int, i: int, j: int, k: int) -> int:
+    return int(load().ht_index_tw(w, i, j, k))
+
+
+def selftest_lane_shift() -> int:
+    bad = C.c_int(-1)
+    check(load().ht_selftest_lane_shift(C.byref(bad)))
+    return bad.value
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return HT_F64
+    if t.dtype == torch.float32:
+        return HT_F32
+    raise TypeError("vectors must be float64 or float32 tensors")
+
+
+def _ptr(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("vectors must be contiguous device tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mesh:
+    """A coarse tetrahedral mesh refined to levels ``min_level..max_level``."""
+
+    def __init__(self, xyz, cells, min_level: int, max_level: int):
+        lib = load()
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self._cells = np.ascontiguousarray(cells, dtype=np.int64)
+        h = C.c_void_p()
+        check(lib.ht_mesh_create(self._xyz.ctypes.data, len(self._xyz),
+                                 self._cells.ctypes.data, len(self._cells),
+                                 min_level, max_level, C.byref(h)))
+        self._h = h
+        self.min_level, self.max_level = min_level, max_level
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ht_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- host ----
+    def info(self, level: int) -> dict:
+        li = _lib.LevelInfo()
+        check(load().ht_mesh_query(self._h, level, C.byref(li)))
+        return {f: getattr(li, f) for f, _ in li._fields_}
+
+    def n_slots(self, level: int) -> int:
+        return self.info(level)["n_slots"]
+
+    def keys(self, level: int, first: int = 0, count: int | None = None):
+        if count is None:
+            count = self.n_slots(level) - first
+        keys = np.empty((count, 8), dtype=np.int64)
+        flags = np.empty(count, dtype=np.uint8)
+        check(load().ht_vertex_keys(self._h, level, first, count,
+                                    keys.ctypes.data, flags.ctypes.data))
+        return keys, flags
+
+    def coords(self, level: int, first: int = 0, count: int | None = None):
+        if count is None:
+            count = self.n_slots(level) - first
+        out = np.empty((count, 3), dtype=np.float64)
+        check(load().ht_vertex_coords(self._h, level, first, count,
+                                      out.ctypes.data))
+        return out
+
+    def slot_index(self, level: int, cell: int, i: int, j: int, k: int) -> int:
+        s = C.c_int64()
+        check(load().ht_slot_index(self._h, level, cell, i, j, k, C.byref(s)))
+        return s.value
+
+    def cell_stencils(self, level: int) -> np.ndarray:
+        out = np.empty((len(self._cells), 16, 15), dtype=np.float64)
+        check(load().ht_cell_stencils(self._h, level, out.ctypes.data))
+        return out
+
+    # -------------------------------------------------------- device ----
+    def new_vector(self, level: int, dtype=None):
+        import torch
+        dtype = torch.float64 if dtype is None else dtype
+        return torch.zeros(self.n_slots(level), dtype=dtype, device="cuda")
+
+    def coords_device(self, level: int, out):
+        check(load().ht_vertex_coords_device(self._h, level, _dtype_code(out),
+                                             _ptr(out), _stream()))
+        return out
+
+    def flags_device(self, level: int, out):
+        check(load().ht_slot_flags_device(self._h, level, _ptr(out),
+                                          _stream()))
+        return out
+
+    def sync(self, level: int, v):
+        check(load().ht_sync(self._h, level, _dtype_code(v), _ptr(v),
+                             _stream()))
+        return v
+
+    def fill_dirichlet(self, level: int, v, value: float = 0.0):
+        check(load().ht_fill_dirichlet(self._h, level, _dtype_code(v), _ptr(v),
+                                       float(value), _stream()))
+        return v
+
+    def lumped_mass(self, level: int, out):
+        check(load().ht_lumped_mass(self._h, level, _dtype_code(out),
+                                    _ptr(out), _stream()))
+        return out
+
+    def norm(self, level: int, v) -> float:
+        r = C.c_double()
+        check(load().ht_norm(self._h, level, _dtype_code(v), _ptr(v),
+                             C.byref(r), _stream()))
+        return r.value
+
+    def dot(self, level: int, a, b) -> float:
+        r = C.c_double()
+        check(load().ht_dot(self._h, level, _dtype_code(a), _ptr(a), _ptr(b),
+                            C.byref(r), _stream()))
+        return r.value
+
+    def apply(self, level: int, x, y):
+        check(load().ht_apply(self._h, level, _dtype_code(x), _ptr(x), _ptr(y),
+                              _stream()))
+        return y
+
+    def residual(self, level: int, u, b, r, want_norm: bool = False):
+        nrm = C.c_double()
+        check(load().ht_residual(self._h, level, _dtype_code(u), _ptr(u),
+                                 _ptr(b), _ptr(r),
+                                 C.byref(nrm) if want_norm else None,
+                                 _stream()))
+        return nrm.value if want_norm else r
+
+    def smooth_jacobi(self, level: int, u, b, omega: float = 2.0 / 3.0,
+                      sweeps: int = 1):
+        check(load().ht_smooth_jacobi(self._h, level, _dtype_code(u),
+                                      float(omega), int(sweeps), _ptr(u),
+                                      _ptr(b), _stream()))
+        return u
+
+    def restrict(self, fine_level: int, r_fine, r_coarse):
+        check(load().ht_restrict(self._h, fine_level, _dtype_code(r_fine),
+                                 _ptr(r_fine), _ptr(r_coarse), _stream()))
+        return r_coarse
+
+    def prolongate_add(self, coarse_level: int, e_coarse, u_fine):
+        check(load().ht_prolongate_add(self._h, coarse_level,
+                                       _dtype_code(e_coarse), _ptr(e_coarse),
+                                       _ptr(u_fine), _stream()))
+        return u_fine
+
+    def coarse_solve(self, level: int, b, u):
+        check(load().ht_coarse_solve(self._h, level, _dtype_code(b), _ptr(b),
+                                     _ptr(u), _stream()))
+        return u
+
+    @staticmethod
+    def cycle_opts(nu1=2, nu2=2, omega=2.0 / 3.0, coarse_level=2):
+        return _lib.CycleOpts(nu1, nu2, omega, coarse_level)
+
+    def vcycle(self, level: int, u, b, nu1=2, nu2=2, omega=2.0 / 3.0,
+               coarse_level=2):
+        o = self.cycle_opts(nu1, nu2, omega, coarse_level)
+        check(load().ht_vcycle(self._h, level, _dtype_code(u), C.byref(o),
+                               _ptr(u), _ptr(b), _stream()))
+        return u
+
+    def solve(self, level: int, u, b, precision=HT_PREC_F64, rel_tol=1e-10,
+              max_cycles=100, nu1=2, nu2=2, omega=2.0 / 3.0, coarse_level=2,
+              use_graph=True, raise_on_fail=True):
+        o = _lib.SolveOpts(self.cycle_opts(nu1, nu2, omega, coarse_level),
+                           precision, rel_tol, max_cycles, int(use_graph))
+        st = _lib.SolveStats()
+        code = load().ht_solve(self._h, level, C.byref(o), _ptr(u), _ptr(b),
+                               C.byref(st), _stream())
+        if code != _lib.HT_ERR_NOT_CONVERGED or raise_on_fail:
+            check(code)
+        return {"cycles": st.cycles, "converged": bool(st.converged),
+                "rel_res": st.rel_res, "seconds": st.seconds,
+                "history": list(st.res_history[:st.cycles + 1])}
+
+    # ----------------------------------------------------- profiling ----
+    def profile(self, enable: bool = True):
+        check(load().ht_profile_enable(self._h, int(enable)))
+
+    def profile_reset(self):
+        check(load().ht_profile_reset(self._h))
+
+    def profile_query(self, prefix: str):
+        ms, n = C.c_double(), C.c_int64()
+        check(load().ht_profile_query(self._h, prefix.encode(), C.byref(ms),
+                                      C.byref(n)))
+        return ms.value, n.value

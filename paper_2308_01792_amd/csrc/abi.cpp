@@ -1,0 +1,945 @@
+// C ABI of the hytet library: argument checking, device upload, launch
+// sequencing of operators, V-cycles, iterative refinement and graphs.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <sstream>
+
+#include "hytet_impl.hpp"
+#include "kernels.hpp"
+
+struct ht_mesh {
+  ht::Mesh m;
+  // (level, J) -> tile list on the device
+  std::map<std::pair<int, int>, std::pair<int2*, int64_t>> tiles;
+  std::map<std::pair<int, int>, int> tuned_J;  // (level, dtype) -> J
+  bool capturing = false;
+};
+
+namespace ht {
+
+static thread_local std::string g_last_error;
+void set_error(int code, const std::string& msg) {
+  (void)code;
+  g_last_error = msg;
+}
+
+static int guard(const std::function<void()>& f) {
+  try {
+    f();
+    return HT_OK;
+  } catch (const Error& e) {
+    set_error(e.code, e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error(HT_ERR_OOM, "host allocation failed");
+    return HT_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_error(HT_ERR_ARG, e.what());
+    return HT_ERR_ARG;
+  } catch (...) {
+    set_error(HT_ERR_ARG, "unknown error");
+    return HT_ERR_ARG;
+  }
+}
+
+static void check_level(const Mesh& m, int level) {
+  if (level < m.min_level || level > m.max_level)
+    throw Error{HT_ERR_LEVEL, "level " + std::to_string(level) +
+                                  " outside [" + std::to_string(m.min_level) +
+                                  ", " + std::to_string(m.max_level) + "]"};
+}
+static void check_dtype(int dtype) {
+  if (dtype != HT_F64 && dtype != HT_F32)
+    throw Error{HT_ERR_ARG, "dtype must be HT_F64 or HT_F32"};
+}
+static void check_ptr(const void* p, const char* what) {
+  if (!p) throw Error{HT_ERR_ARG, std::string(what) + " is NULL"};
+  if (reinterpret_cast<uintptr_t>(p) % 256)
+    throw Error{HT_ERR_ARG, std::string(what) + " is not 256-byte aligned"};
+}
+static size_t esize(int dtype) { return dtype == HT_F64 ? 8 : 4; }
+
+int64_t level_slots(const Mesh& m, int level) {
+  return m.nc * make_layout(level).stride;
+}
+
+template <typename T>
+static T* dalloc(size_t count, bool zero = true) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{HT_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
+                                " bytes failed"};
+  }
+  if (zero) HT_CHECK_HIP(hipMemset(p, 0, count * sizeof(T)));
+  return (T*)p;
+}
+template <typename T>
+static T* upload(const std::vector<T>& v) {
+  T* p = dalloc<T>(v.size(), false);
+  if (!v.empty())
+    HT_CHECK_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+static const int kJ[] = {4, 8, 16};
+
+static std::vector<int2> make_tiles(int n, int J) {
+  std::vector<int2> t;
+  for (int tj = 0; J * tj <= n; ++tj)
+    for (int ti = 0; 62 * ti + J * tj <= n; ++ti) t.push_back(make_int2(62 * ti, J * tj));
+  return t;
+}
+
+static int64_t partials_needed(const ht_mesh* h, int level) {
+  const Mesh& m = h->m;
+  const int n = 1 << level;
+  int64_t cell_blocks = 0;
+  for (int J : kJ) cell_blocks = std::max<int64_t>(cell_blocks, m.nc * (int64_t)make_tiles(n, J).size());
+  const int64_t fp = n_tri(n - 2), total = m.n_faces * fp + m.n_edges * std::max(n - 1, 0) + m.n_verts;
+  const int64_t exch_blocks = (total + 255) / 256;
+  const int64_t elem_blocks = m.nc * n_tri(n + 1);
+  return std::max(cell_blocks + exch_blocks, elem_blocks) + 64;
+}
+
+void ensure_uploaded_h(ht_mesh* h) {
+  Mesh& m = h->m;
+  if (m.uploaded) return;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    throw Error{HT_ERR_STATE, "no HIP device available"};
+  }
+  HT_CHECK_HIP(hipGetDevice(&m.device));
+  m.d_cls = upload(m.cls);
+  std::vector<DevPrim> dp(m.prims.size());
+  std::vector<DevInc> di;
+  for (size_t p = 0; p < m.prims.size(); ++p) {
+    const Prim& P = m.prims[p];
+    if (P.inc.size() > 32000)
+      throw Error{HT_ERR_MESH, "too many cells around one primitive"};
+    dp[p].inc_begin = (int32_t)di.size();
+    dp[p].inc_count = (int16_t)P.inc.size();
+    dp[p].dim = (int8_t)P.dim;
+    dp[p].boundary = P.boundary ? 1 : 0;
+    dp[p].inv_diag_unit = P.boundary ? 0.0 : 1.0 / P.diag_unit;
+    for (const Incidence& I : P.inc) {
+      DevInc d;
+      d.cell = I.cell;
+      d.lv[0] = I.lv[0]; d.lv[1] = I.lv[1]; d.lv[2] = I.lv[2];
+      d.cls = I.cls;
+      di.push_back(d);
+    }
+  }
+  m.d_prim = upload(dp);
+  m.d_inc = upload(di);
+  std::vector<double> cx(m.nc * 12);
+  std::vector<int8_t> co(m.nc * 4);
+  for (int64_t c = 0; c < m.nc; ++c) {
+    int ord[4] = {0, 1, 2, 3};
+    std::sort(ord, ord + 4, [&](int a, int b) { return m.cells[c].gv[a] < m.cells[c].gv[b]; });
+    for (int q = 0; q < 4; ++q) {
+      co[4 * c + q] = (int8_t)ord[q];
+      for (int a = 0; a < 3; ++a) cx[12 * c + 3 * q + a] = m.xyz[3 * m.cells[c].gv[ord[q]] + a];
+    }
+  }
+  m.d_cell_xyz = upload(cx);
+  m.d_cell_order = upload(co);
+  m.d_w64.assign(m.max_level + 1, nullptr);
+  m.d_w32.assign(m.max_level + 1, nullptr);
+  int64_t pcap = 0;
+  for (int l = m.min_level; l <= m.max_level; ++l) {
+    std::vector<double> w;
+    level_scaled_stencils(m, l, w);
+    std::vector<float> wf(w.begin(), w.end());
+    m.d_w64[l] = upload(w);
+    m.d_w32[l] = upload(wf);
+    for (int J : kJ) {
+      auto t = make_tiles(1 << l, J);
+      h->tiles[{l, J}] = {upload(t), (int64_t)t.size()};
+    }
+    pcap = std::max(pcap, partials_needed(h, l));
+  }
+  m.d_partials = dalloc<double>(pcap);
+  m.partials_cap = pcap;
+  m.d_scalar = dalloc<double>(16);
+  HT_CHECK_HIP(hipHostMalloc((void**)&m.h_scalar, 16 * sizeof(double), hipHostMallocDefault));
+  HT_CHECK_HIP(hipStreamCreateWithFlags(&m.capture_stream, hipStreamNonBlocking));
+  m.work64.assign(m.max_level + 1, LevelWork{});
+  m.work32.assign(m.max_level + 1, LevelWork{});
+  m.uploaded = true;
+}
+
+// --------------------------------------------------------- profiling ----
+struct Prof {
+  ht_mesh* h;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Prof(ht_mesh* h_, const char* n, hipStream_t s_) : h(h_), name(n), s(s_) {
+    if (h->m.profiling && !h->capturing) {
+      HT_CHECK_HIP(hipEventCreate(&a));
+      HT_CHECK_HIP(hipEventCreate(&b));
+      HT_CHECK_HIP(hipEventRecord(a, s));
+    }
+  }
+  ~Prof() {
+    if (a) {
+      (void)hipEventRecord(b, s);
+      h->m.prof.push_back({name, a, b});
+    }
+  }
+};
+
+static void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{HT_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+// -------------------------------------------------------- operators -----
+static int choose_J(ht_mesh* h, int level, int dtype) {
+  auto it = h->tuned_J.find({level, dtype});
+  if (it != h->tuned_J.end()) return it->second;
+  return 8;
+}
+
+static CellArgs cell_args(ht_mesh* h, int level, int dtype, int J,
+                          const void* x, void* y, const void* b, double omega) {
+  Mesh& m = h->m;
+  const CellLayout L = make_layout(level);
+  CellArgs a{};
+  a.x = x; a.y = y; a.b = b;
+  a.w = dtype == HT_F64 ? (const void*)m.d_w64[level] : (const void*)m.d_w32[level];
+  a.cls = m.d_cls;
+  a.partials = m.d_partials;
+  auto& t = h->tiles.at({level, J});
+  a.tiles = t.first;
+  a.ntiles = t.second;
+  a.nblocks = m.nc * t.second;
+  a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
+  a.n = L.n;
+  a.omega = omega;
+  a.nscale = (double)L.n;
+  return a;
+}
+
+static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
+                          const void* b, double omega, double* partials) {
+  Mesh& m = h->m;
+  const CellLayout L = make_layout(level);
+  const int n = L.n;
+  ExchArgs a{};
+  a.y = y; a.u = u; a.b = b;
+  a.prim = m.d_prim; a.inc = m.d_inc;
+  a.partials = partials;
+  a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
+  a.n = n;
+  a.n_faces = m.n_faces; a.n_edges = m.n_edges;
+  a.face_pts = n_tri(n - 2);
+  a.face_end = m.n_faces * a.face_pts;
+  a.edge_end = a.face_end + m.n_edges * std::max(n - 1, 0);
+  a.total = a.edge_end + m.n_verts;
+  a.omega = omega;
+  a.nscale = (double)n;
+  return a;
+}
+
+// One operator pass (cell kernel + ghost exchange).  For OP_RESID the norm
+// of the result lands in m.d_scalar[slot] (device) when want_norm.
+static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
+                    void* y, const void* b, double omega, hipStream_t s,
+                    bool want_norm = false, int scalar_slot = 0) {
+  Mesh& m = h->m;
+  const int J = choose_J(h, level, dtype);
+  CellArgs ca = cell_args(h, level, dtype, J, x, y, b, omega);
+  {
+    Prof p(h, op == OP_APPLY ? "cell_apply" : op == OP_RESID ? "cell_residual" : "cell_jacobi", s);
+    launch_cell(dtype, op, J, ca, s);
+    check_launch();
+  }
+  ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
+                          m.d_partials + ca.nblocks);
+  if (op == OP_RESID) ea.u = x;
+  {
+    Prof p(h, "exchange", s);
+    launch_exchange(dtype, op, ea, s);
+    check_launch();
+  }
+  if (op == OP_RESID && want_norm) {
+    const int64_t cnt = ca.nblocks + (ea.total + 255) / 256;
+    Prof p(h, "norm_sum", s);
+    launch_sum_partials(m.d_partials, cnt, m.d_scalar + scalar_slot, true, s);
+    check_launch();
+  }
+}
+
+static void exch_only(ht_mesh* h, int level, int dtype, int op, void* v,
+                      double fill, hipStream_t s) {
+  ExchArgs ea = exch_args(h, level, v, nullptr, nullptr, 0.0, h->m.d_partials);
+  ea.fill = fill;
+  Prof p(h, op == OP_SYNC ? "sync" : "fill", s);
+  launch_exchange(dtype, op, ea, s);
+  check_launch();
+}
+
+static ElemArgs elem_args(ht_mesh* h, int level) {
+  Mesh& m = h->m;
+  const CellLayout L = make_layout(level);
+  ElemArgs a{};
+  a.cls = m.d_cls;
+  a.partials = m.d_partials;
+  a.cell_xyz = m.d_cell_xyz;
+  a.cell_order = m.d_cell_order;
+  a.ncells = m.nc;
+  a.n = L.n;
+  a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
+  a.nscale = (double)L.n;
+  return a;
+}
+
+static void flat(ht_mesh* h, int level, int dto, int dti, int fop, void* out,
+                 const void* in, hipStream_t s) {
+  FlatArgs a{out, in, level_slots(h->m, level)};
+  Prof p(h, "flat", s);
+  launch_flat(dto, dti, fop, a, s);
+  check_launch();
+}
+
+static void zero_guess_sweep(ht_mesh* h, int level, int dtype, double omega,
+                             void* u, const void* b, hipStream_t s) {
+  ElemArgs a = elem_args(h, level);
+  a.out = u; a.in0 = b; a.alpha = omega;
+  Prof p(h, "zero_guess", s);
+  launch_elem(dtype, EOP_ZERO_GUESS, a, s);
+  check_launch();
+}
+
+static void restrict_pass(ht_mesh* h, int fine, int dtype, const void* rf,
+                          void* rc, hipStream_t s) {
+  Mesh& m = h->m;
+  const CellLayout Lf = make_layout(fine), Lc = make_layout(fine - 1);
+  XferArgs a{};
+  a.src = rf; a.dst = rc; a.cls = m.d_cls; a.ncells = m.nc;
+  a.nf = Lf.n; a.nc_ = Lc.n;
+  a.stride_f = Lf.stride; a.off_s0_f = Lf.off_s0; a.off_s1_f = Lf.off_s1;
+  a.stride_c = Lc.stride; a.off_s0_c = Lc.off_s0; a.off_s1_c = Lc.off_s1;
+  {
+    Prof p(h, "restrict", s);
+    launch_restrict(dtype, a, s);
+    check_launch();
+  }
+  ExchArgs ea = exch_args(h, fine - 1, rc, nullptr, nullptr, 0.0, m.d_partials);
+  Prof p(h, "exchange", s);
+  launch_exchange(dtype, OP_RESTRICT, ea, s);
+  check_launch();
+}
+
+static void prolong_pass(ht_mesh* h, int coarse, int dtype, const void* ec,
+                         void* uf, hipStream_t s) {
+  Mesh& m = h->m;
+  const CellLayout Lf = make_layout(coarse + 1), Lc = make_layout(coarse);
+  XferArgs a{};
+  a.src = ec; a.dst = uf; a.cls = m.d_cls; a.ncells = m.nc;
+  a.nf = Lf.n; a.nc_ = Lc.n;
+  a.stride_f = Lf.stride; a.off_s0_f = Lf.off_s0; a.off_s1_f = Lf.off_s1;
+  a.stride_c = Lc.stride; a.off_s0_c = Lc.off_s0; a.off_s1_c = Lc.off_s1;
+  Prof p(h, "prolongate", s);
+  launch_prolong(dtype, a, s);
+  check_launch();
+}
+
+static CoarseSolver& coarse_solver(ht_mesh* h, int level) {
+  Mesh& m = h->m;
+  auto it = m.coarse.find(level);
+  if (it != m.coarse.end()) return it->second;
+  CoarseSolver& cs = m.coarse[level];
+  build_coarse_solver(m, level, cs);
+  cs.d_inv = upload(cs.inv);
+  cs.d_owner = upload(cs.owner_slot);
+  cs.d_copy_ptr = upload(cs.copy_ptr);
+  cs.d_copy_slot = upload(cs.copy_slot);
+  cs.d_rhs = dalloc<double>(std::max<int64_t>(cs.ndof, 1));
+  return cs;
+}
+
+// u_I = A_II^-1 b_I, Dirichlet slots of u untouched (assumed zero data).
+static void coarse_fast(ht_mesh* h, int level, int dtype, const void* b,
+                        void* u, hipStream_t s) {
+  CoarseSolver& cs = coarse_solver(h, level);
+  CoarseArgs a{b, u, cs.d_inv, cs.d_owner, cs.d_copy_ptr, cs.d_copy_slot, cs.d_rhs, cs.ndof};
+  Prof p(h, "coarse_solve", s);
+  launch_coarse(dtype, a, s);
+  check_launch();
+}
+
+static LevelWork& work(ht_mesh* h, int level, int dtype) {
+  Mesh& m = h->m;
+  LevelWork& w = (dtype == HT_F64 ? m.work64 : m.work32)[level];
+  if (!w.t) {
+    const size_t n = level_slots(m, level) * esize(dtype);
+    w.u = dalloc<char>(n);
+    w.b = dalloc<char>(n);
+    w.t = dalloc<char>(n);
+  }
+  return w;
+}
+
+// Weighted Jacobi sweeps between two buffers; returns the buffer holding the
+// result (cur or other).
+static void* sweeps(ht_mesh* h, int level, int dtype, double omega, int count,
+                    void* cur, void* other, const void* b, hipStream_t s) {
+  for (int k = 0; k < count; ++k) {
+    op_pass(h, level, dtype, OP_JACOBI, cur, other, b, omega, s);
+    std::swap(cur, other);
+  }
+  return cur;
+}
+
+// V(nu1, nu2) on `level`: iterate in u (or t), returns the buffer with the
+// new iterate.  zero_guess: the incoming iterate is zero.
+static void* vcycle_impl(ht_mesh* h, int level, int dtype,
+                         const ht_cycle_opts& o, void* u, void* t,
+                         const void* b, bool zero_guess, hipStream_t s) {
+  if (level == o.coarse_level) {
+    coarse_fast(h, level, dtype, b, u, s);
+    return u;
+  }
+  void* cur = u;
+  void* other = t;
+  int todo = o.nu1;
+  if (zero_guess) {
+    if (todo > 0) {
+      zero_guess_sweep(h, level, dtype, o.omega, cur, b, s);
+      --todo;
+    } else {
+      flat(h, level, dtype, dtype, FOP_ZERO, cur, nullptr, s);
+    }
+  }
+  cur = sweeps(h, level, dtype, o.omega, todo, cur, other, b, s);
+  other = (cur == u) ? t : u;
+  op_pass(h, level, dtype, OP_RESID, cur, other, b, 0.0, s);
+  LevelWork& wc = work(h, level - 1, dtype);
+  restrict_pass(h, level, dtype, other, wc.b, s);
+  void* ec = vcycle_impl(h, level - 1, dtype, o, wc.u, wc.t, wc.b, true, s);
+  prolong_pass(h, level - 1, dtype, ec, cur, s);
+  return sweeps(h, level, dtype, o.omega, o.nu2, cur, other, b, s);
+}
+
+static void check_cycle(const Mesh& m, int level, const ht_cycle_opts* o) {
+  if (!o) throw Error{HT_ERR_ARG, "cycle options are NULL"};
+  if (o->coarse_level < m.min_level || o->coarse_level > level)
+    throw Error{HT_ERR_LEVEL, "coarse_level outside [min_level, level]"};
+  if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 > 64)
+    throw Error{HT_ERR_ARG, "sweep counts must be in [0, 64]"};
+  if (!(o->omega > 0.0 && o->omega < 2.0))
+    throw Error{HT_ERR_ARG, "omega must lie in (0, 2)"};
+}
+
+// Top-level V-cycle on caller buffers (u, b).
+static void vcycle_top(ht_mesh* h, int level, int dtype, const ht_cycle_opts& o,
+                       void* u, const void* b, bool zero_guess, hipStream_t s) {
+  LevelWork& w = work(h, level, dtype);
+  void* res = vcycle_impl(h, level, dtype, o, u, w.t, b, zero_guess, s);
+  if (res != u) flat(h, level, dtype, dtype, FOP_COPY, u, res, s);
+}
+
+static double read_scalar(ht_mesh* h, int slot, hipStream_t s) {
+  Mesh& m = h->m;
+  HT_CHECK_HIP(hipMemcpyAsync(m.h_scalar + slot, m.d_scalar + slot, sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+  HT_CHECK_HIP(hipStreamSynchronize(s));
+  return m.h_scalar[slot];
+}
+
+static double norm_of(ht_mesh* h, int level, int dtype, const void* a,
+                      const void* b, hipStream_t s, bool sq) {
+  ElemArgs ea = elem_args(h, level);
+  ea.in0 = a; ea.in1 = b;
+  {
+    Prof p(h, "dot", s);
+    launch_elem(dtype, EOP_DOT, ea, s);
+    check_launch();
+  }
+  const int64_t cnt = h->m.nc * n_tri(make_layout(level).n + 1);
+  launch_sum_partials(h->m.d_partials, cnt, h->m.d_scalar + 1, sq, s);
+  check_launch();
+  return read_scalar(h, 1, s);
+}
+
+// Capture `body` into a graph cached under `key` and launch it on s.
+static void run_graph(ht_mesh* h, const std::string& key,
+                      const std::function<void(hipStream_t)>& body,
+                      hipStream_t s) {
+  Mesh& m = h->m;
+  auto it = m.graphs.find(key);
+  if (it == m.graphs.end()) {
+    hipGraph_t g = nullptr;
+    h->capturing = true;
+    HT_CHECK_HIP(hipStreamBeginCapture(m.capture_stream, hipStreamCaptureModeRelaxed));
+    try {
+      body(m.capture_stream);
+    } catch (...) {
+      hipGraph_t dummy;
+      (void)hipStreamEndCapture(m.capture_stream, &dummy);
+      h->capturing = false;
+      throw;
+    }
+    HT_CHECK_HIP(hipStreamEndCapture(m.capture_stream, &g));
+    h->capturing = false;
+    GraphEntry ge;
+    HT_CHECK_HIP(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
+    HT_CHECK_HIP(hipGraphDestroy(g));
+    it = m.graphs.emplace(key, ge).first;
+  }
+  HT_CHECK_HIP(hipGraphLaunch(it->second.exec, s));
+}
+
+}  // namespace ht
+
+using namespace ht;
+
+// ================================================================= ABI ====
+extern "C" {
+
+const char* ht_last_error(void) { return g_last_error.c_str(); }
+int ht_version(void) { return 1; }
+int64_t ht_index_tw(int64_t w, int64_t i, int64_t j, int64_t k) {
+  return t_w(w, i, j, k);
+}
+
+int ht_mesh_create(const double* xyz, int64_t nv, const int64_t* cells,
+                   int64_t nc, int min_level, int max_level, ht_mesh** out) {
+  return guard([&] {
+    if (!out) throw Error{HT_ERR_ARG, "out is NULL"};
+    *out = nullptr;
+    auto h = std::make_unique<ht_mesh>();
+    build_mesh(h->m, xyz, nv, cells, nc, min_level, max_level);
+    *out = h.release();
+  });
+}
+
+int ht_mesh_destroy(ht_mesh* h) {
+  return guard([&] {
+    if (!h) return;
+    Mesh& m = h->m;
+    if (m.uploaded) {
+      (void)hipDeviceSynchronize();
+      for (auto& kv : m.graphs) (void)hipGraphExecDestroy(kv.second.exec);
+      for (auto& kv : h->tiles) (void)hipFree(kv.second.first);
+      for (auto* p : m.d_w64) if (p) (void)hipFree(p);
+      for (auto* p : m.d_w32) if (p) (void)hipFree(p);
+      for (auto* list : {&m.work64, &m.work32})
+        for (auto& w : *list) { (void)hipFree(w.u); (void)hipFree(w.b); (void)hipFree(w.t); }
+      for (auto& kv : m.coarse) {
+        (void)hipFree(kv.second.d_inv); (void)hipFree(kv.second.d_owner);
+        (void)hipFree(kv.second.d_copy_ptr); (void)hipFree(kv.second.d_copy_slot);
+        (void)hipFree(kv.second.d_rhs);
+      }
+      for (auto& e : m.prof) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+      (void)hipFree(m.d_cls); (void)hipFree(m.d_prim); (void)hipFree(m.d_inc);
+      (void)hipFree(m.d_cell_xyz); (void)hipFree(m.d_cell_order);
+      (void)hipFree(m.d_partials); (void)hipFree(m.d_scalar);
+      (void)hipHostFree(m.h_scalar);
+      (void)hipStreamDestroy(m.capture_stream);
+    }
+    delete h;
+  });
+}
+
+int ht_mesh_query(const ht_mesh* h, int level, ht_level_info* info) {
+  return guard([&] {
+    if (!h || !info) throw Error{HT_ERR_ARG, "NULL argument"};
+    const Mesh& m = h->m;
+    check_level(m, level);
+    const CellLayout L = make_layout(level);
+    const int n = L.n;
+    info->n_slots = m.nc * L.stride;
+    info->cell_stride = L.stride;
+    info->n_cells = m.nc;
+    info->n_faces = m.n_faces;
+    info->n_edges = m.n_edges;
+    info->n_vertices = m.n_verts;
+    int64_t uniq = m.nc * n_tet(n - 3), dofs = uniq;
+    for (const Prim& p : m.prims) {
+      const int64_t pts = p.dim == 2 ? n_tri(n - 2) : (p.dim == 1 ? std::max(n - 1, 0) : 1);
+      uniq += pts;
+      if (!p.boundary) dofs += pts;
+    }
+    info->n_unique = uniq;
+    info->n_dofs = dofs;
+  });
+}
+
+int ht_vertex_keys(const ht_mesh* h, int level, int64_t first, int64_t count,
+                   int64_t* keys, uint8_t* flags) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    check_level(h->m, level);
+    const int64_t ns = level_slots(h->m, level);
+    if (first < 0 || count < 0 || first + count > ns)
+      throw Error{HT_ERR_ARG, "slot range out of bounds"};
+    parallel_for(count, [&](int64_t lo, int64_t hi) {
+      for (int64_t s = lo; s < hi; ++s) {
+        int64_t k[8];
+        uint8_t f;
+        slot_key(h->m, level, first + s, k, &f);
+        if (keys) std::memcpy(keys + 8 * s, k, sizeof(k));
+        if (flags) flags[s] = f;
+      }
+    });
+  });
+}
+
+int ht_vertex_coords(const ht_mesh* h, int level, int64_t first, int64_t count,
+                     double* xyz) {
+  return guard([&] {
+    if (!h || !xyz) throw Error{HT_ERR_ARG, "NULL argument"};
+    check_level(h->m, level);
+    const int64_t ns = level_slots(h->m, level);
+    if (first < 0 || count < 0 || first + count > ns)
+      throw Error{HT_ERR_ARG, "slot range out of bounds"};
+    parallel_for(count, [&](int64_t lo, int64_t hi) {
+      for (int64_t s = lo; s < hi; ++s) slot_coords(h->m, level, first + s, xyz + 3 * s);
+    });
+  });
+}
+
+int ht_slot_index(const ht_mesh* h, int level, int64_t cell, int i, int j,
+                  int k, int64_t* slot) {
+  return guard([&] {
+    if (!h || !slot) throw Error{HT_ERR_ARG, "NULL argument"};
+    check_level(h->m, level);
+    const CellLayout L = make_layout(level);
+    if (cell < 0 || cell >= h->m.nc || i < 0 || j < 0 || k < 0 || i + j + k > L.n)
+      throw Error{HT_ERR_ARG, "index outside the cell closure"};
+    *slot = cell * L.stride + slot_in_cell(L, i, j, k);
+  });
+}
+
+int ht_cell_stencils(const ht_mesh* h, int level, double* out) {
+  return guard([&] {
+    if (!h || !out) throw Error{HT_ERR_ARG, "NULL argument"};
+    check_level(h->m, level);
+    std::vector<double> w;
+    level_scaled_stencils(h->m, level, w);
+    std::memcpy(out, w.data(), w.size() * sizeof(double));
+  });
+}
+
+int ht_vertex_coords_device(ht_mesh* h, int level, int dtype, void* xyz_dev,
+                            ht_stream stream) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    check_level(h->m, level);
+    check_dtype(dtype);
+    check_ptr(xyz_dev, "xyz_dev");
+    ensure_uploaded_h(h);
+    ElemArgs a = elem_args(h, level);
+    a.out = xyz_dev;
+    a.alpha = std::ldexp(1.0, -level);
+    launch_elem(dtype, EOP_COORDS, a, (hipStream_t)stream);
+    check_launch();
+  });
+}
+
+int ht_slot_flags_device(ht_mesh* h, int level, uint8_t* flags_dev,
+                         ht_stream stream) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    check_level(h->m, level);
+    check_ptr(flags_dev, "flags_dev");
+    ensure_uploaded_h(h);
+    HT_CHECK_HIP(hipMemsetAsync(flags_dev, HT_SLOT_PAD, level_slots(h->m, level),
+                                (hipStream_t)stream));
+    ElemArgs a = elem_args(h, level);
+    a.out = flags_dev;
+    launch_elem(HT_F64, EOP_FLAGS, a, (hipStream_t)stream);
+    check_launch();
+  });
+}
+
+#define HT_DEV_PROLOGUE(level, dtype)      \
+  if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"}; \
+  check_level(h->m, level);                \
+  check_dtype(dtype);                      \
+  ensure_uploaded_h(h);                    \
+  hipStream_t s = (hipStream_t)stream;
+
+int ht_sync(ht_mesh* h, int level, int dtype, void* v, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(v, "v");
+    exch_only(h, level, dtype, OP_SYNC, v, 0.0, s);
+  });
+}
+
+int ht_fill_dirichlet(ht_mesh* h, int level, int dtype, void* v, double value,
+                      ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(v, "v");
+    exch_only(h, level, dtype, OP_FILL, v, value, s);
+  });
+}
+
+int ht_lumped_mass(ht_mesh* h, int level, int dtype, void* mvec, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(mvec, "m");
+    ElemArgs a = elem_args(h, level);
+    a.out = mvec;
+    a.nscale = std::ldexp(1.0, -3 * level);
+    launch_elem(dtype, EOP_MASS, a, s);
+    check_launch();
+  });
+}
+
+int ht_norm(ht_mesh* h, int level, int dtype, const void* v, double* norm,
+            ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(v, "v");
+    if (!norm) throw Error{HT_ERR_ARG, "norm is NULL"};
+    *norm = norm_of(h, level, dtype, v, v, s, true);
+  });
+}
+
+int ht_dot(ht_mesh* h, int level, int dtype, const void* a, const void* b,
+           double* dot, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(a, "a");
+    check_ptr(b, "b");
+    if (!dot) throw Error{HT_ERR_ARG, "dot is NULL"};
+    *dot = norm_of(h, level, dtype, a, b, s, false);
+  });
+}
+
+int ht_apply(ht_mesh* h, int level, int dtype, const void* x, void* y,
+             ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(x, "x");
+    check_ptr(y, "y");
+    if (x == y) throw Error{HT_ERR_ARG, "x and y must not alias"};
+    op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s);
+  });
+}
+
+int ht_residual(ht_mesh* h, int level, int dtype, const void* u, const void* b,
+                void* r, double* norm, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(u, "u");
+    check_ptr(b, "b");
+    check_ptr(r, "r");
+    if (r == u || r == b) throw Error{HT_ERR_ARG, "r must not alias u or b"};
+    op_pass(h, level, dtype, OP_RESID, u, r, b, 0.0, s, norm != nullptr, 0);
+    if (norm) *norm = read_scalar(h, 0, s);
+  });
+}
+
+int ht_smooth_jacobi(ht_mesh* h, int level, int dtype, double omega, int nsw,
+                     void* u, const void* b, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(u, "u");
+    check_ptr(b, "b");
+    if (nsw < 0) throw Error{HT_ERR_ARG, "sweeps must be >= 0"};
+    LevelWork& w = work(h, level, dtype);
+    void* res = sweeps(h, level, dtype, omega, nsw, u, w.t, b, s);
+    if (res != u) flat(h, level, dtype, dtype, FOP_COPY, u, res, s);
+  });
+}
+
+int ht_restrict(ht_mesh* h, int fine_level, int dtype, const void* rf, void* rc,
+                ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(fine_level, dtype);
+    check_level(h->m, fine_level - 1);
+    check_ptr(rf, "r_fine");
+    check_ptr(rc, "r_coarse");
+    restrict_pass(h, fine_level, dtype, rf, rc, s);
+  });
+}
+
+int ht_prolongate_add(ht_mesh* h, int coarse_level, int dtype, const void* ec,
+                      void* uf, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(coarse_level, dtype);
+    check_level(h->m, coarse_level + 1);
+    check_ptr(ec, "e_coarse");
+    check_ptr(uf, "u_fine");
+    prolong_pass(h, coarse_level, dtype, ec, uf, s);
+  });
+}
+
+int ht_coarse_solve(ht_mesh* h, int level, int dtype, const void* b, void* u,
+                    ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(b, "b");
+    check_ptr(u, "u");
+    // rhs = b - A u_B (u with its interior zeroed), then u_I = A_II^-1 rhs
+    LevelWork& w = work(h, level, dtype);
+    flat(h, level, dtype, dtype, FOP_COPY, w.u, u, s);
+    ElemArgs a = elem_args(h, level);
+    a.out = w.u;
+    launch_elem(dtype, EOP_ZERO_INTERIOR, a, s);
+    check_launch();
+    op_pass(h, level, dtype, OP_RESID, w.u, w.t, b, 0.0, s);
+    coarse_fast(h, level, dtype, w.t, u, s);
+  });
+}
+
+int ht_vcycle(ht_mesh* h, int level, int dtype, const ht_cycle_opts* o, void* u,
+              const void* b, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_cycle(h->m, level, o);
+    check_ptr(u, "u");
+    check_ptr(b, "b");
+    if (level == o->coarse_level) {
+      if (ht_coarse_solve(h, level, dtype, b, u, stream) != HT_OK)
+        throw Error{HT_ERR_HIP, g_last_error};
+      return;
+    }
+    vcycle_top(h, level, dtype, *o, u, b, false, s);
+  });
+}
+
+int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
+             const void* b, ht_solve_stats* st, ht_stream stream) {
+  int rc = guard([&] {
+    HT_DEV_PROLOGUE(level, HT_F64);
+    if (!o || !st) throw Error{HT_ERR_ARG, "NULL options or stats"};
+    check_cycle(h->m, level, &o->cyc);
+    check_ptr(u, "u");
+    check_ptr(b, "b");
+    if (o->max_cycles < 0 || o->max_cycles > 256)
+      throw Error{HT_ERR_ARG, "max_cycles must be in [0, 256]"};
+    if (o->precision != HT_PREC_F64 && o->precision != HT_PREC_MIXED)
+      throw Error{HT_ERR_ARG, "precision must be HT_PREC_F64 or HT_PREC_MIXED"};
+    if (level == o->cyc.coarse_level && o->precision == HT_PREC_MIXED)
+      throw Error{HT_ERR_ARG, "mixed precision needs level > coarse_level"};
+    std::memset(st, 0, sizeof(*st));
+    auto t0 = std::chrono::steady_clock::now();
+    const double bnorm = norm_of(h, level, HT_F64, b, b, s, true);
+    const double scale = bnorm > 0 ? 1.0 / bnorm : 1.0;
+    LevelWork& w64 = work(h, level, HT_F64);
+    // residual of the initial iterate
+    op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, s, true, 0);
+    double rel = read_scalar(h, 0, s) * scale;
+    st->res_history[0] = rel;
+    int k = 0;
+    const bool mixed = o->precision == HT_PREC_MIXED;
+    LevelWork* w32 = mixed ? &work(h, level, HT_F32) : nullptr;
+    auto step = [&](hipStream_t ss) {
+      if (!mixed) {
+        vcycle_top(h, level, HT_F64, o->cyc, u, b, false, ss);
+        op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, ss, true, 0);
+      } else {
+        // FP32 correction of the FP64 residual held in w64.t
+        flat(h, level, HT_F32, HT_F64, FOP_COPY, w32->b, w64.t, ss);
+        void* e = vcycle_impl(h, level, HT_F32, o->cyc, w32->u, w32->t, w32->b, true, ss);
+        flat(h, level, HT_F64, HT_F32, FOP_ADD, u, e, ss);
+        op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, ss, true, 0);
+      }
+      HT_CHECK_HIP(hipMemcpyAsync(h->m.h_scalar, h->m.d_scalar, sizeof(double),
+                                  hipMemcpyDeviceToHost, ss));
+    };
+    std::ostringstream key;
+    key << "solve:" << level << ':' << o->precision << ':' << o->cyc.nu1 << ':'
+        << o->cyc.nu2 << ':' << o->cyc.omega << ':' << o->cyc.coarse_level << ':'
+        << u << ':' << b;
+    // all allocations and host setup happen before any capture
+    coarse_solver(h, o->cyc.coarse_level);
+    for (int l = o->cyc.coarse_level; l <= level; ++l) {
+      work(h, l, HT_F64);
+      if (mixed) work(h, l, HT_F32);
+    }
+    while (rel > o->rel_tol && k < o->max_cycles && std::isfinite(rel)) {
+      if (o->use_graph) run_graph(h, key.str(), step, s);
+      else step(s);
+      HT_CHECK_HIP(hipStreamSynchronize(s));
+      rel = h->m.h_scalar[0] * scale;
+      ++k;
+      st->res_history[k] = rel;
+    }
+    st->cycles = k;
+    st->rel_res = rel;
+    st->converged = rel <= o->rel_tol;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!st->converged)
+      throw Error{HT_ERR_NOT_CONVERGED, "relative residual " + std::to_string(rel) +
+                                            " after " + std::to_string(k) + " cycles"};
+  });
+  return rc;
+}
+
+int ht_profile_enable(ht_mesh* h, int enable) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    h->m.profiling = enable != 0;
+  });
+}
+
+int ht_profile_reset(ht_mesh* h) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    (void)hipDeviceSynchronize();
+    for (auto& e : h->m.prof) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    h->m.prof.clear();
+  });
+}
+
+int ht_profile_query(ht_mesh* h, const char* prefix, double* ms, int64_t* launches) {
+  return guard([&] {
+    if (!h || !prefix || !ms || !launches) throw Error{HT_ERR_ARG, "NULL argument"};
+    double tot = 0;
+    int64_t cnt = 0;
+    const size_t pl = std::strlen(prefix);
+    for (auto& e : h->m.prof) {
+      if (e.name.compare(0, pl, prefix) != 0) continue;
+      HT_CHECK_HIP(hipEventSynchronize(e.b));
+      float t = 0;
+      HT_CHECK_HIP(hipEventElapsedTime(&t, e.a, e.b));
+      tot += t;
+      ++cnt;
+    }
+    *ms = tot;
+    *launches = cnt;
+  });
+}
+
+int ht_selftest_lane_shift(int* mismatches) {
+  return guard([&] {
+    if (!mismatches) throw Error{HT_ERR_ARG, "NULL argument"};
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+      (void)hipGetLastError();
+      throw Error{HT_ERR_STATE, "no HIP device available"};
+    }
+    int* d = dalloc<int>(128);
+    launch_lane_selftest(d, 0);
+    check_launch();
+    int hbuf[128];
+    HT_CHECK_HIP(hipMemcpy(hbuf, d, sizeof(hbuf), hipMemcpyDeviceToHost));
+    (void)hipFree(d);
+    int bad = 0;
+    for (int l = 0; l < 64; ++l) {
+      const int prev = l == 0 ? 0 : l;         // value of lane l-1 is l
+      const int next = l == 63 ? 0 : l + 2;    // value of lane l+1 is l+2
+      bad += hbuf[l] != prev;
+      bad += hbuf[64 + l] != next;
+    }
+    *mismatches = bad;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Kernel argument blocks and launchers shared by kernels.hip and abi.cpp.
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <hip/hip_vector_types.h>
+
+#include "hytet_impl.hpp"
+
+namespace ht {
+
+enum { OP_APPLY = 0, OP_RESID = 1, OP_JACOBI = 2, OP_SYNC = 3, OP_FILL = 4,
+       OP_RESTRICT = 5 };
+enum { EOP_ZERO_GUESS = 0, EOP_MASS = 1, EOP_ZERO_INTERIOR = 2, EOP_DOT = 3,
+       EOP_FLAGS = 4, EOP_COORDS = 5 };
+enum { FOP_COPY = 0, FOP_ADD = 1, FOP_ZERO = 2 };
+enum { kMaxInc = 128 };  // incident cells per shared primitive (checked)
+
+struct CellArgs {
+  const void* x;        // operand (u for residual / Jacobi)
+  void* y;              // output
+  const void* b;        // right-hand side (residual / Jacobi)
+  const void* w;        // level-scaled class stencils [nc][16][15]
+  const ClassInfo* cls; // [nc][16]
+  double* partials;     // per-block norm partials (residual)
+  const int2* tiles;    // (i0, j0) of the non-empty tiles of one cell
+  int64_t ntiles, nblocks;
+  int64_t stride, off_s0, off_s1;
+  int n;
+  double omega, nscale; // nscale = 2^l (inverse diagonal scale)
+};
+
+struct ExchArgs {
+  void* y;
+  const void* u;
+  const void* b;
+  const DevPrim* prim;
+  const DevInc* inc;
+  double* partials;
+  int64_t stride, off_s0, off_s1;
+  int n;
+  int64_t n_faces, n_edges;
+  int64_t face_pts, face_end, edge_end, total;
+  double omega, nscale, fill;
+};
+
+struct XferArgs {
+  const void* src;
+  void* dst;
+  const ClassInfo* cls;
+  int64_t ncells;
+  int nf, nc_;          // fine and coarse n
+  int64_t stride_f, off_s0_f, off_s1_f;
+  int64_t stride_c, off_s0_c, off_s1_c;
+};
+
+struct ElemArgs {
+  void* out;
+  const void* in0;
+  const void* in1;
+  const ClassInfo* cls;
+  double* partials;
+  const double* cell_xyz;
+  const int8_t* cell_order;
+  int64_t ncells;
+  int n;
+  int64_t stride, off_s0, off_s1;
+  double alpha, nscale;
+};
+
+struct FlatArgs {
+  void* out;
+  const void* in;
+  int64_t count;
+};
+
+struct CoarseArgs {
+  const void* b;
+  void* u;
+  const double* inv;
+  const int64_t* owner;
+  const int64_t* copy_ptr;
+  const int64_t* copy_slot;
+  double* rhs;
+  int64_t ndof;
+};
+
+void launch_cell(int dtype, int op, int J, const CellArgs& a, hipStream_t s);
+void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s);
+void launch_restrict(int dtype, const XferArgs& a, hipStream_t s);
+void launch_prolong(int dtype, const XferArgs& a, hipStream_t s);
+void launch_elem(int dtype, int eop, const ElemArgs& a, hipStream_t s);
+void launch_flat(int dto, int dti, int fop, const FlatArgs& a, hipStream_t s);
+void launch_sum_partials(const double* p, int64_t count, double* out, bool sq,
+                         hipStream_t s);
+void launch_coarse(int dtype, const CoarseArgs& a, hipStream_t s);
+void launch_lane_selftest(int* out, hipStream_t s);
+
+}  // namespace ht

@@ -1,0 +1,291 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+FP64 results must agree with the oracle to 1e-12 relative (max-norm over the
+vector, relative to the oracle's max-norm); FP32 results are checked against
+a stated bound derived from single precision (a 15-term stencil sum of
+O(1) terms: 1e-5 relative).  Every output must be consistent (all copies of
+a shared micro-vertex equal).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2308_01792_amd as ht  # noqa: E402
+from tests.gpu_support import Pair, rel_err  # noqa: E402
+from workloads import fields  # noqa: E402
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+APPLY_CASES = [("ref_tet", 4), ("ref_tet", 1), ("kuhn_cube", 5),
+               ("kuhn_211", 3), ("jittered_288", 2), ("jittered_288", 3),
+               ("jittered_288", 4), ("jittered_222", 3), ("slab_3_11", 3),
+               ("slab_1_1", 3), ("slab_2_7", 0), ("jittered_222", 6)]
+
+_PAIRS = {}
+
+
+def pair(name, max_level, min_level=0):
+    key = (name, max_level, min_level)
+    if key not in _PAIRS:
+        _PAIRS[key] = Pair(name, max_level, min_level)
+    return _PAIRS[key]
+
+
+def test_lane_shift_selftest():
+    assert ht.selftest_lane_shift() == 0
+
+
+@pytest.mark.parametrize("name,level", APPLY_CASES)
+def test_apply_fp64(name, level):
+    P = pair(name, level, level)
+    S = P.S(level)
+    x = fields.uniform_values(S.mesh.num_vertices, 4)   # boundary data too
+    xg = P.to_gpu(level, x)
+    yg = torch.full_like(xg, np.nan)
+    P.m.apply(level, xg, yg)
+    torch.cuda.synchronize()
+    y = P.from_gpu(level, yg)
+    ref = S.apply(x)
+    assert np.isfinite(y).all()
+    assert rel_err(y, ref) <= FP64_TOL
+    assert (y[S.dirichlet] == 0).all()
+
+
+@pytest.mark.parametrize("name,level", [("ref_tet", 4), ("jittered_288", 4),
+                                        ("kuhn_cube", 5)])
+def test_apply_fp32(name, level):
+    P = pair(name, level, level)
+    S = P.S(level)
+    x = fields.uniform_values(S.mesh.num_vertices, 4)
+    xg = P.to_gpu(level, x, torch.float32)
+    yg = torch.zeros_like(xg)
+    P.m.apply(level, xg, yg)
+    y = P.from_gpu(level, yg)
+    err = rel_err(y, S.apply(x.astype(np.float32).astype(np.float64)))
+    print(f"fp32 apply {name} l{level}: rel err {err:.2e}")
+    assert err <= FP32_TOL
+
+
+def test_apply_is_deterministic():
+    P = pair("jittered_288", 4, 4)
+    x = P.to_gpu(4, fields.uniform_values(P.S(4).mesh.num_vertices, 9))
+    y1, y2 = torch.zeros_like(x), torch.zeros_like(x)
+    P.m.apply(4, x, y1)
+    P.m.apply(4, x, y2)
+    assert torch.equal(y1, y2)
+
+
+@pytest.mark.parametrize("name,level", [("ref_tet", 4), ("jittered_288", 4),
+                                        ("slab_3_11", 3)])
+def test_residual_and_norm(name, level):
+    P = pair(name, level, level)
+    S = P.S(level)
+    u = fields.uniform_values(S.mesh.num_vertices, 1)
+    b = fields.uniform_values(S.mesh.num_vertices, 2)
+    r = torch.zeros(P.m.n_slots(level), dtype=torch.float64, device="cuda")
+    nrm = P.m.residual(level, P.to_gpu(level, u), P.to_gpu(level, b), r,
+                       want_norm=True)
+    ref = S.residual(u, b)
+    assert rel_err(P.from_gpu(level, r), ref) <= FP64_TOL
+    assert abs(nrm - np.linalg.norm(ref)) <= FP64_TOL * np.linalg.norm(ref)
+
+
+def test_norm_and_dot_count_unique_interior_dofs():
+    P = pair("jittered_288", 3, 3)
+    S = P.S(3)
+    a = fields.uniform_values(S.mesh.num_vertices, 5)
+    b = fields.uniform_values(S.mesh.num_vertices, 6)
+    ag, bg = P.to_gpu(3, a), P.to_gpu(3, b)
+    I = S.interior
+    assert P.m.norm(3, ag) == pytest.approx(np.linalg.norm(a[I]), rel=1e-13)
+    assert P.m.dot(3, ag, bg) == pytest.approx(a[I] @ b[I], rel=1e-12)
+
+
+@pytest.mark.parametrize("run", [1, 2])
+def test_c1_jacobi_ten_sweeps(run):
+    """C1: reference tet, level 4, omega = 2/3, ten sweeps.  Run 1: b = 0,
+    u0 ~ U[-1,1] (seed 0) with zero boundary; run 2: b ~ U[-1,1] (seed 1),
+    u0 = 0."""
+    P = pair("ref_tet", 4, 4)
+    S = P.S(4)
+    N = S.mesh.num_vertices
+    if run == 1:
+        u0 = np.where(S.dirichlet, 0.0, fields.uniform_values(N, 0))
+        b = np.zeros(N)
+    else:
+        u0 = np.zeros(N)
+        b = fields.uniform_values(N, 1)
+    ug = P.to_gpu(4, u0)
+    P.m.smooth_jacobi(4, ug, P.to_gpu(4, b), 2.0 / 3.0, 10)
+    ref = S.jacobi(u0, b, 2.0 / 3.0, 10)
+    assert rel_err(P.from_gpu(4, ug), ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("name,level,sweeps", [("jittered_288", 4, 3),
+                                               ("kuhn_211", 3, 2),
+                                               ("slab_3_11", 3, 1)])
+def test_jacobi_sweeps(name, level, sweeps):
+    P = pair(name, level, level)
+    S = P.S(level)
+    N = S.mesh.num_vertices
+    u0 = fields.uniform_values(N, 7)        # non-zero Dirichlet data kept
+    b = fields.uniform_values(N, 8)
+    for dtype, tol in ((torch.float64, FP64_TOL), (torch.float32, 20 * FP32_TOL)):
+        ug = P.to_gpu(level, u0, dtype)
+        P.m.smooth_jacobi(level, ug, P.to_gpu(level, b, dtype), 2.0 / 3.0, sweeps)
+        assert rel_err(P.from_gpu(level, ug), S.jacobi(u0, b, 2.0 / 3.0, sweeps)) <= tol
+
+
+@pytest.mark.parametrize("name,fine", [("jittered_288", 3), ("jittered_288", 4),
+                                       ("ref_tet", 4), ("slab_3_11", 3),
+                                       ("kuhn_211", 2), ("jittered_222", 1)])
+def test_restrict(name, fine):
+    P = pair(name, fine, fine - 1)
+    r = fields.uniform_values(P.S(fine).mesh.num_vertices, 3)
+    r = np.where(P.S(fine).dirichlet, 0.0, r)
+    rc = torch.full((P.m.n_slots(fine - 1),), np.nan, dtype=torch.float64,
+                    device="cuda")
+    P.m.restrict(fine, P.to_gpu(fine, r), rc)
+    assert rel_err(P.from_gpu(fine - 1, rc), P.H.restrict(fine, r)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("name,coarse", [("jittered_288", 2), ("jittered_288", 3),
+                                         ("ref_tet", 3), ("slab_3_11", 2),
+                                         ("jittered_222", 0)])
+def test_prolongate_add(name, coarse):
+    P = pair(name, coarse + 1, coarse)
+    e = fields.uniform_values(P.S(coarse).mesh.num_vertices, 4)
+    e = np.where(P.S(coarse).dirichlet, 0.0, e)
+    u = fields.uniform_values(P.S(coarse + 1).mesh.num_vertices, 5)
+    ug = P.to_gpu(coarse + 1, u)
+    P.m.prolongate_add(coarse, P.to_gpu(coarse, e), ug)
+    ref = P.H.prolongate_add(coarse, e, u)
+    assert rel_err(P.from_gpu(coarse + 1, ug), ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("name,level", [("jittered_288", 2), ("kuhn_cube", 2),
+                                        ("slab_3_11", 2), ("ref_tet", 3)])
+def test_coarse_solve(name, level):
+    P = pair(name, level, level)
+    S = P.S(level)
+    N = S.mesh.num_vertices
+    b = fields.uniform_values(N, 11)
+    u0 = np.where(S.dirichlet, fields.uniform_values(N, 12), 0.0)
+    ug = P.to_gpu(level, u0)
+    P.m.coarse_solve(level, P.to_gpu(level, b), ug)
+    ref = P.H.coarse_solve(level, u0, b)
+    assert rel_err(P.from_gpu(level, ug), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("name,level", [("jittered_288", 4), ("kuhn_cube", 5),
+                                        ("slab_3_11", 4)])
+def test_vcycle_iterates(name, level):
+    """Five V(2,2) cycles from u0 = 0 with b = m * f: every iterate matches."""
+    P = pair(name, level, 2)
+    S = P.S(level)
+    f = fields.uniform_values(S.mesh.num_vertices, 5)
+    b = S.lumped_mass * f
+    bg = P.to_gpu(level, b)
+    ug = torch.zeros_like(bg)
+    u = np.zeros_like(b)
+    for k in range(5):
+        P.m.vcycle(level, ug, bg, 2, 2, 2.0 / 3.0, 2)
+        u = P.H.vcycle(level, u, b, 2, 2, 2.0 / 3.0, 2)
+        assert rel_err(P.from_gpu(level, ug), u) <= FP64_TOL, k
+
+
+def test_vcycle_fp32_iterates():
+    P = pair("jittered_288", 4, 2)
+    S = P.S(4)
+    b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5)
+    bg = P.to_gpu(4, b, torch.float32)
+    ug = torch.zeros_like(bg)
+    u = np.zeros_like(b)
+    for _ in range(3):
+        P.m.vcycle(4, ug, bg, 2, 2, 2.0 / 3.0, 2)
+        u = P.H.vcycle(4, u, b, 2, 2, 2.0 / 3.0, 2)
+    err = rel_err(P.from_gpu(4, ug), u)
+    print(f"fp32 V-cycle iterate 3: rel err {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_lumped_mass():
+    P = pair("jittered_288", 3, 3)
+    mg = torch.zeros(P.m.n_slots(3), dtype=torch.float64, device="cuda")
+    P.m.lumped_mass(3, mg)
+    assert rel_err(P.from_gpu(3, mg), P.S(3).lumped_mass) <= 1e-14
+
+
+def test_sync_and_fill_dirichlet():
+    P = pair("jittered_288", 3, 3)
+    S = P.S(3)
+    idx, flags = P.slot_map(3)
+    rnd = torch.rand(P.m.n_slots(3), dtype=torch.float64, device="cuda",
+                     generator=torch.Generator("cuda").manual_seed(0))
+    P.m.sync(3, rnd)
+    v = P.from_gpu(3, rnd)                 # asserts consistency
+    P.m.fill_dirichlet(3, rnd, 0.25)
+    w = P.from_gpu(3, rnd)
+    assert (w[S.dirichlet] == 0.25).all()
+    assert np.array_equal(w[S.interior], v[S.interior])
+
+
+def test_coords_device_and_flags_device():
+    P = pair("jittered_288", 3, 3)
+    n = P.m.n_slots(3)
+    X = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    P.m.coords_device(3, X)
+    host = P.m.coords(3)
+    idx, flags = P.slot_map(3)
+    real = idx >= 0
+    assert np.abs(X.view(-1, 3).cpu().numpy()[real] - host[real]).max() <= 1e-15
+    F = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    P.m.flags_device(3, F)
+    assert np.array_equal(F.cpu().numpy(), flags)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_solve_fp64(use_graph):
+    P = pair("jittered_288", 4, 2)
+    S = P.S(4)
+    b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5)
+    bg = P.to_gpu(4, b)
+    ug = torch.zeros_like(bg)
+    st = P.m.solve(4, ug, bg, ht.HT_PREC_F64, 1e-10, 100, use_graph=use_graph)
+    uo, hist = P.H.solve(4, b, rel_tol=1e-10, coarse_level=2)
+    assert st["converged"] and abs(st["cycles"] - (len(hist) - 1)) <= 1
+    assert np.allclose(st["history"][:5], hist[:5], rtol=1e-9, atol=0)
+    assert rel_err(P.from_gpu(4, ug), uo) <= 1e-9
+
+
+def test_solve_graph_replay_matches_eager():
+    P = pair("jittered_288", 4, 2)
+    S = P.S(4)
+    b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5)
+    bg = P.to_gpu(4, b)
+    res = []
+    for g in (False, True, True):
+        ug = torch.zeros_like(bg)
+        st = P.m.solve(4, ug, bg, ht.HT_PREC_F64, 1e-10, 100, use_graph=g)
+        torch.cuda.synchronize()
+        res.append((ug.clone(), st["history"]))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][0], res[2][0])
+    assert res[0][1] == res[1][1] == res[2][1]
+
+
+def test_solve_mixed_precision():
+    P = pair("jittered_288", 4, 2)
+    S = P.S(4)
+    b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5)
+    bg = P.to_gpu(4, b)
+    ug = torch.zeros_like(bg)
+    st = P.m.solve(4, ug, bg, ht.HT_PREC_MIXED, 1e-10, 100)
+    uo, _ = P.H.solve(4, b, rel_tol=1e-12, coarse_level=2)
+    err = rel_err(P.from_gpu(4, ug), uo)
+    print(f"mixed solve: {st['cycles']} steps, rel res {st['rel_res']:.2e}, "
+          f"error vs FP64 oracle {err:.2e}")
+    assert st["converged"] and st["rel_res"] <= 1e-10
+    assert err <= 1e-8
