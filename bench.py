@@ -41,6 +41,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-level", type=int, default=5)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run 3 plain device copies of one level vector "
+                        "(counter calibration for rocprofv3 --pmc)")
     return p.parse_args()
 
 
@@ -97,6 +100,11 @@ def main():
     mesh.fill_dirichlet(L, x, 0.0)
     y = torch.zeros_like(x)
     torch.cuda.synchronize()
+    t0 = time.time()
+    rows64 = mesh.autotune(L, ht.HT_F64)
+    rows32 = mesh.autotune(L, ht.HT_F32)
+    log(f"autotuned tile rows: f64 {rows64}, f32 {rows32} "
+        f"({time.time() - t0:.1f} s)")
 
     # ---------------- headline: FP64 apply -------------------------------
     log(f"FP64 apply: {args.warmup} warmup + {args.steps} timed steps, "
@@ -129,6 +137,12 @@ def main():
     achieved = BYTES_PER_DOF_F64 * ndof / (cell_avg * 1e-3) / 1e9
     log(f"cell kernel {cell_avg:.3f} ms ({achieved:.0f} GB/s algorithmic), "
         f"exchange {exch_avg:.3f} ms")
+
+    if args.copy_calibration:
+        log(f"plain copy calibration: {nslot * 8} bytes read + written per copy")
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
 
     # ---------------- FP32 apply ------------------------------------------
     x32, y32 = x.float(), torch.zeros(nslot, dtype=torch.float32, device=dev)
@@ -165,9 +179,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None,
-                     "kernel": "k_cell<double, apply>",
+                     "kernel": f"k_cell<double, apply, {rows64}>",
                      "bytes_per_launch": BYTES_PER_DOF_F64 * ndof},
         "apply_hbm_frac": round(gdofs * BYTES_PER_DOF_F64 / HBM_PEAK_GBS, 4),
+        "tile_rows": {"f64": rows64, "f32": rows32},
         "kernel_ms": {"cell_apply": round(cell_avg, 4),
                       "exchange": round(exch_avg, 4)},
         "apply_f32": {"ms": round(ms32, 4),

@@ -199,6 +199,21 @@ int ht_vcycle(ht_mesh* mesh, int level, int dtype, const ht_cycle_opts* opts,
 int ht_solve(ht_mesh* mesh, int level, const ht_solve_opts* opts, void* u,
              const void* b, ht_solve_stats* stats, ht_stream stream);
 
+/* ------------------------------------------------------------- tuning -- */
+/* The stencil kernel runs one wavefront per tile of 64 i-points x R rows,
+ * marching in k.  R in {4, 8, 16} trades register pressure against halo
+ * re-reads.  ht_set_tile_rows fixes R for (level, dtype); ht_get_tile_rows
+ * reports the current choice (default 8). */
+int ht_set_tile_rows(ht_mesh* mesh, int level, int dtype, int rows);
+int ht_get_tile_rows(const ht_mesh* mesh, int level, int dtype, int* rows);
+/* Autotuner: times every R on the live apply at (level, dtype) on `stream`
+ * (two scratch vectors are allocated and freed), keeps the fastest and
+ * returns it in *rows.  With cache_path != NULL a text cache keyed by
+ * (gfx arch, level, dtype, cells, cell stride) is read first and appended
+ * to after tuning.  Synchronises. */
+int ht_autotune(ht_mesh* mesh, int level, int dtype, const char* cache_path,
+                int* rows, ht_stream stream);
+
 /* ---------------------------------------------------------- profiling -- */
 /* Record HIP events around every kernel the library launches. */
 int ht_profile_enable(ht_mesh* mesh, int enable);

@@ -221,6 +221,22 @@ class Mesh:
                 "rel_res": st.rel_res, "seconds": st.seconds,
                 "history": list(st.res_history[:st.cycles + 1])}
 
+    # -------------------------------------------------------- tuning ----
+    def set_tile_rows(self, level: int, dtype_code: int, rows: int):
+        check(load().ht_set_tile_rows(self._h, level, dtype_code, rows))
+
+    def tile_rows(self, level: int, dtype_code: int) -> int:
+        r = C.c_int()
+        check(load().ht_get_tile_rows(self._h, level, dtype_code, C.byref(r)))
+        return r.value
+
+    def autotune(self, level: int, dtype_code: int, cache_path=None) -> int:
+        r = C.c_int()
+        check(load().ht_autotune(self._h, level, dtype_code,
+                                 cache_path.encode() if cache_path else None,
+                                 C.byref(r), _stream()))
+        return r.value
+
     # ----------------------------------------------------- profiling ----
     def profile(self, enable: bool = True):
         check(load().ht_profile_enable(self._h, int(enable)))

@@ -73,6 +73,9 @@ SIGNATURES = {
     "ht_vcycle": (I, [P, I, I, C.POINTER(CycleOpts), P, P, P]),
     "ht_solve": (I, [P, I, C.POINTER(SolveOpts), P, P,
                      C.POINTER(SolveStats), P]),
+    "ht_set_tile_rows": (I, [P, I, I, I]),
+    "ht_get_tile_rows": (I, [P, I, I, C.POINTER(I)]),
+    "ht_autotune": (I, [P, I, I, C.c_char_p, C.POINTER(I), P]),
     "ht_profile_enable": (I, [P, I]),
     "ht_profile_query": (I, [P, C.c_char_p, C.POINTER(D), C.POINTER(L)]),
     "ht_profile_reset": (I, [P]),

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <cstdio>
+#include <cstdlib>
 #include <sstream>
 
 #include "hytet_impl.hpp"
@@ -880,6 +882,103 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
                                             " after " + std::to_string(k) + " cycles"};
   });
   return rc;
+}
+
+int ht_set_tile_rows(ht_mesh* h, int level, int dtype, int rows) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    check_level(h->m, level);
+    check_dtype(dtype);
+    if (rows != 4 && rows != 8 && rows != 16)
+      throw Error{HT_ERR_ARG, "tile rows must be 4, 8 or 16"};
+    h->tuned_J[{level, dtype}] = rows;
+  });
+}
+
+int ht_get_tile_rows(const ht_mesh* h, int level, int dtype, int* rows) {
+  return guard([&] {
+    if (!h || !rows) throw Error{HT_ERR_ARG, "NULL argument"};
+    check_level(h->m, level);
+    check_dtype(dtype);
+    auto it = h->tuned_J.find({level, dtype});
+    *rows = it == h->tuned_J.end() ? 8 : it->second;
+  });
+}
+
+int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
+                int* rows, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    // cache: lines "<gfx arch> <level> <dtype> <cells> <stride> <rows>"
+    hipDeviceProp_t prop;
+    HT_CHECK_HIP(hipGetDeviceProperties(&prop, h->m.device));
+    const CellLayout L = make_layout(level);
+    std::ostringstream key;
+    key << prop.gcnArchName << ' ' << level << ' ' << dtype << ' ' << h->m.nc
+        << ' ' << L.stride;
+    if (cache_path) {
+      FILE* f = std::fopen(cache_path, "r");
+      if (f) {
+        char line[512];
+        while (std::fgets(line, sizeof line, f)) {
+          std::string ln(line);
+          const size_t sp = ln.find_last_of(' ');
+          if (sp != std::string::npos && ln.compare(0, sp, key.str()) == 0) {
+            const int J = std::atoi(ln.c_str() + sp + 1);
+            if (J == 4 || J == 8 || J == 16) {
+              h->tuned_J[{level, dtype}] = J;
+              if (rows) *rows = J;
+              std::fclose(f);
+              return;
+            }
+          }
+        }
+        std::fclose(f);
+      }
+    }
+    const size_t bytes = level_slots(h->m, level) * esize(dtype);
+    void* x = dalloc<char>(bytes);
+    void* y = dalloc<char>(bytes);
+    hipEvent_t e0, e1;
+    HT_CHECK_HIP(hipEventCreate(&e0));
+    HT_CHECK_HIP(hipEventCreate(&e1));
+    const bool was_profiling = h->m.profiling;
+    h->m.profiling = false;
+    int best = 8;
+    float best_ms = 1e30f;
+    try {
+      for (int J : kJ) {
+        h->tuned_J[{level, dtype}] = J;
+        for (int rep = 0; rep < 2; ++rep) op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s);
+        HT_CHECK_HIP(hipEventRecord(e0, s));
+        const int reps = 5;
+        for (int rep = 0; rep < reps; ++rep) op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s);
+        HT_CHECK_HIP(hipEventRecord(e1, s));
+        HT_CHECK_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        HT_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = J; }
+      }
+    } catch (...) {
+      h->m.profiling = was_profiling;
+      (void)hipFree(x); (void)hipFree(y);
+      throw;
+    }
+    h->m.profiling = was_profiling;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    h->tuned_J[{level, dtype}] = best;
+    if (rows) *rows = best;
+    if (cache_path) {
+      FILE* f = std::fopen(cache_path, "a");
+      if (f) {
+        std::fprintf(f, "%s %d\n", key.str().c_str(), best);
+        std::fclose(f);
+      }
+    }
+  });
 }
 
 int ht_profile_enable(ht_mesh* h, int enable) {

@@ -93,13 +93,49 @@ template <typename T>
 __device__ __forceinline__ T ldv(const T* p) { return *p; }
 
 // ----------------------------------------------------------- cell kernel --
+// Buffer loads/stores with a per-cell range: an offset at or beyond the range
+// reads 0 and drops the store, which replaces per-lane branches.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+#define HT_OOB 0x80000000u
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p,
+                                                           int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                           (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void bload(double& v, __amdgpu_buffer_rsrc_t r,
+                                      unsigned off) {
+  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bload(float& v, __amdgpu_buffer_rsrc_t r,
+                                      unsigned off) {
+  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r,
+                                       unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r,
+                                       unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
+// One wave = one tile of 64 consecutive i (62 outputs, one halo lane on each
+// side) and J rows j0..j0+J-1, marching k upwards with the planes k-1, k,
+// k+1 of rows j0-1..j0+J in registers; i +- 1 neighbours come from DPP.
+//
+// Points on the cell's faces get the cell's partial row.  On rows with
+// j >= 1, k >= 1 and line end e >= 2 only two lanes can be surface points:
+// i = 0 (face i = 0) and i = e (slanted face).  Their partial row equals the
+// interior row (values outside the closure load as 0) plus a 7-term
+// correction over the in-face offsets with uniform weights.  Rows with
+// j == 0, k == 0 or e <= 1 take per-lane class weights from LDS.
 template <typename T, int OP, int J>
 __global__ __launch_bounds__(64) void k_cell(CellArgs a) {
   __shared__ T wtab[16 * 15];
+  __shared__ T wdel[14];  // in-face corrections: face i = 0, slanted face
   const int lane = threadIdx.x;
-  // XCD-aware block order: hardware dispatches block b to XCD b % 8; give
-  // each XCD a contiguous run of (cell, tile) work so the tiles that share
-  // halo rows share an L2.
+  // XCD-aware block order: block b runs on XCD b % 8; give each XCD a
+  // contiguous run of (cell, tile) work so tiles sharing halo rows share L2.
   const int64_t nb = a.nblocks;
   const int64_t chunk = (nb + 7) / 8;
   const int64_t w = (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
@@ -107,97 +143,153 @@ __global__ __launch_bounds__(64) void k_cell(CellArgs a) {
   const int64_t cell = w / a.ntiles;
   const int2 tile = a.tiles[w % a.ntiles];
   const int i0 = tile.x, j0 = tile.y;
-  const Lay L{a.n, a.stride, a.off_s0, a.off_s1};
-  const int n = L.n;
-  const T* __restrict__ x = (const T*)a.x + cell * L.stride;
-  T* __restrict__ y = (T*)a.y + cell * L.stride;
-  const T* __restrict__ bv = (const T*)a.b + (a.b ? cell * L.stride : 0);
+  const int n = a.n;
+  const int64_t bytes = a.stride * (int64_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc((T*)a.y + cell * a.stride, bytes);
+  const __amdgpu_buffer_rsrc_t rb =
+      make_rsrc(a.b ? (const T*)a.b + cell * a.stride : (const T*)a.y, bytes);
   const T* wc = (const T*)a.w + cell * 240;
   for (int t = lane; t < 240; t += 64) wtab[t] = wc[t];
+  if (lane < 14) {
+    const int d0[7] = {0, 3, 4, 5, 6, 11, 12}, d8[7] = {0, 7, 8, 9, 10, 11, 12};
+    const int d = lane < 7 ? d0[lane] : d8[lane - 7];
+    const int cls = lane < 7 ? 1 : 8;
+    wdel[lane] = wc[cls * 15 + d] - wc[d];
+  }
   __syncthreads();
-  T w0 = wc[0], w1 = wc[1], w2 = wc[2], w3 = wc[3], w4 = wc[4], w5 = wc[5],
-    w6 = wc[6], w7 = wc[7], w8 = wc[8], w9 = wc[9], w10 = wc[10],
-    w11 = wc[11], w12 = wc[12], w13 = wc[13], w14 = wc[14];
+  const T w0 = wc[0], w1 = wc[1], w2 = wc[2], w3 = wc[3], w4 = wc[4],
+          w5 = wc[5], w6 = wc[6], w7 = wc[7], w8 = wc[8], w9 = wc[9],
+          w10 = wc[10], w11 = wc[11], w12 = wc[12], w13 = wc[13], w14 = wc[14];
   const T omega_invd = (T)(a.omega * a.nscale * a.cls[cell * 16].inv_diag_unit);
+  const int off_s0 = (int)a.off_s0, off_s1 = (int)a.off_s1;
 
   const int i = i0 - 1 + lane;
-  const bool out_lane = lane >= 1 && lane <= 62;
-  T xm[J + 2], xc[J + 2], xp[J + 2];
-  auto load_row = [&](int j, int k) -> T {
-    if (j < 0 || k < 0 || i < 0) return (T)0;
-    const int e = n - j - k;
-    if (i > e) return (T)0;
-    const RowBase rb = row_base(L, j, k);
-    return x[row_slot(rb, i)];
+  const bool is0 = (i == 0);
+  const unsigned out_mask = (lane >= 1 && lane <= 62) ? 0u : HT_OOB;
+  // Offsets of the rows j0-1 .. j0+J of plane kk.  Row j of a plane: main
+  // block base mb(j) (element of i = 0 if it were stored there), S0 and S1
+  // entries sa(j), sb(j); consecutive rows differ by the main-block row
+  // length (n-1-kk-j) and by 1 in S0/S1.
+  auto plane_offsets = [&](int kk, unsigned (&o)[J + 2]) {
+    const int w1 = n - 1;
+    int mb = (int)(n_tet(w1) - n_tet(w1 - kk)) - 1;
+    int sa = off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - kk));
+    int sb = off_s1 + (int)(n_tri(n) - n_tri(n - kk));
+    const int jf = j0 - 1;
+    if (jf > 0) {
+      mb += jf * (w1 - kk) - jf * (jf - 1) / 2;
+      sa += jf;
+      sb += jf;
+    }
+#pragma unroll
+    for (int r = 0; r < J + 2; ++r) {
+      const int j = jf + r;
+      const int e = n - j - kk;
+      unsigned off = HT_OOB;
+      if (j >= 0 && e >= 0 && kk <= n) {
+        int el = (i == e) ? sb : mb + i;
+        el = is0 ? sa : el;
+        off = ((unsigned)i <= (unsigned)e) ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB;
+      }
+      o[r] = off;
+      if (j >= 0) {
+        mb += w1 - kk - j;
+        ++sa;
+        ++sb;
+      }
+    }
   };
+
+  T xm[J + 2], xc[J + 2], xp[J + 2];
+  unsigned oc[J + 2];
+  plane_offsets(0, oc);
 #pragma unroll
   for (int r = 0; r < J + 2; ++r) {
     xm[r] = (T)0;
-    xc[r] = load_row(j0 - 1 + r, 0);
+    bload(xc[r], rx, oc[r]);
   }
   double nsq = 0.0;
   const int kmax = n - i0 - j0;
   for (int k = 0; k <= kmax; ++k) {
+    unsigned op[J + 2];
+    plane_offsets(k + 1, op);
 #pragma unroll
-    for (int r = 0; r < J + 2; ++r) xp[r] = load_row(j0 - 1 + r, k + 1);
+    for (int r = 0; r < J + 2; ++r) bload(xp[r], rx, op[r]);
 #pragma unroll
     for (int rr = 0; rr < J; ++rr) {
       const int j = j0 + rr;
       const int e = n - j - k;
-      if (e < i0) break;  // this and all further rows end before the tile
-      // centre row (j, k) and its neighbours
-      const T c = xc[rr + 1];
-      T v[15];
-      v[0] = c;
-      v[1] = lane_next(c);            // ( 1, 0, 0)
-      v[2] = lane_prev(c);            // (-1, 0, 0)
-      v[3] = xc[rr + 2];              // ( 0, 1, 0)
-      v[4] = xc[rr];                  // ( 0,-1, 0)
-      v[5] = xp[rr + 1];              // ( 0, 0, 1)
-      v[6] = xm[rr + 1];              // ( 0, 0,-1)
-      v[7] = lane_prev(xc[rr + 2]);   // (-1, 1, 0)
-      v[8] = lane_next(xc[rr]);       // ( 1,-1, 0)
-      v[9] = lane_prev(xp[rr + 1]);   // (-1, 0, 1)
-      v[10] = lane_next(xm[rr + 1]);  // ( 1, 0,-1)
-      v[11] = xp[rr];                 // ( 0,-1, 1)
-      v[12] = xm[rr + 2];             // ( 0, 1,-1)
-      v[13] = lane_next(xp[rr]);      // ( 1,-1, 1)
-      v[14] = lane_prev(xm[rr + 2]);  // (-1, 1,-1)
-      T acc = w0 * v[0];
-      acc += w1 * v[1]; acc += w2 * v[2]; acc += w3 * v[3];
-      acc += w4 * v[4]; acc += w5 * v[5]; acc += w6 * v[6];
-      acc += w7 * v[7]; acc += w8 * v[8]; acc += w9 * v[9];
-      acc += w10 * v[10]; acc += w11 * v[11]; acc += w12 * v[12];
-      acc += w13 * v[13]; acc += w14 * v[14];
-      const bool valid = out_lane && i >= 0 && i <= e;
-      const int cls = (i == 0) | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3);
-      if (valid && cls != 0) {
-        // point on a face/edge/vertex of the cell: partial row of the cell
-        const T* wt = wtab + cls * 15;
-        T s = wt[0] * v[0];
-#pragma unroll
-        for (int d = 1; d < 15; ++d) s += wt[d] * v[d];
-        acc = s;
-      }
-      if (valid) {
-        const RowBase rb = row_base(L, j, k);
-        const int32_t sl = row_slot(rb, i);
-        T out = acc;
-        if (OP == OP_RESID) {
-          if (cls == 0) {
-            out = bv[sl] - acc;
-            nsq += (double)out * (double)out;
+      if (e >= i0) {
+        const T c = xc[rr + 1];
+        const T v1 = lane_next(c), v2 = lane_prev(c);
+        const T v3 = xc[rr + 2], v4 = xc[rr];
+        const T v5 = xp[rr + 1], v6 = xm[rr + 1];
+        const T v7 = lane_prev(xc[rr + 2]), v8 = lane_next(xc[rr]);
+        const T v9 = lane_prev(xp[rr + 1]), v10 = lane_next(xm[rr + 1]);
+        const T v11 = xp[rr], v12 = xm[rr + 2];
+        const T v13 = lane_next(xp[rr]), v14 = lane_prev(xm[rr + 2]);
+        T acc = w0 * c;
+        acc = fma(w1, v1, acc); acc = fma(w2, v2, acc); acc = fma(w3, v3, acc);
+        acc = fma(w4, v4, acc); acc = fma(w5, v5, acc); acc = fma(w6, v6, acc);
+        acc = fma(w7, v7, acc); acc = fma(w8, v8, acc); acc = fma(w9, v9, acc);
+        acc = fma(w10, v10, acc); acc = fma(w11, v11, acc);
+        acc = fma(w12, v12, acc); acc = fma(w13, v13, acc);
+        acc = fma(w14, v14, acc);
+        bool surf;
+        if (j == 0 || k == 0 || e <= 1) {
+          const int cls = (int)is0 | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3);
+          const T* wt = wtab + cls * 15;
+          T sacc = wt[0] * c;
+          sacc = fma(wt[1], v1, sacc); sacc = fma(wt[2], v2, sacc);
+          sacc = fma(wt[3], v3, sacc); sacc = fma(wt[4], v4, sacc);
+          sacc = fma(wt[5], v5, sacc); sacc = fma(wt[6], v6, sacc);
+          sacc = fma(wt[7], v7, sacc); sacc = fma(wt[8], v8, sacc);
+          sacc = fma(wt[9], v9, sacc); sacc = fma(wt[10], v10, sacc);
+          sacc = fma(wt[11], v11, sacc); sacc = fma(wt[12], v12, sacc);
+          sacc = fma(wt[13], v13, sacc); sacc = fma(wt[14], v14, sacc);
+          acc = sacc;
+          surf = cls != 0;
+        } else {
+          const bool ise = (i == e);
+          if (i0 == 0) {  // face i = 0: class-1 minus interior weights
+            T cc = wdel[0] * c;
+            cc = fma(wdel[1], v3, cc); cc = fma(wdel[2], v4, cc);
+            cc = fma(wdel[3], v5, cc); cc = fma(wdel[4], v6, cc);
+            cc = fma(wdel[5], v11, cc); cc = fma(wdel[6], v12, cc);
+            acc = is0 ? acc + cc : acc;
           }
-        } else if (OP == OP_JACOBI) {
-          if (cls == 0) out = c + omega_invd * (bv[sl] - acc);
+          if (e <= i0 + 61) {  // slanted face: class-8 minus interior weights
+            T cc = wdel[7] * c;
+            cc = fma(wdel[8], v7, cc); cc = fma(wdel[9], v8, cc);
+            cc = fma(wdel[10], v9, cc); cc = fma(wdel[11], v10, cc);
+            cc = fma(wdel[12], v11, cc); cc = fma(wdel[13], v12, cc);
+            acc = ise ? acc + cc : acc;
+          }
+          surf = is0 || ise;
         }
-        y[sl] = out;
+        const unsigned so = oc[rr + 1] | out_mask;
+        T out = acc;
+        if (OP == OP_RESID || OP == OP_JACOBI) {
+          T bval;
+          bload(bval, rb, oc[rr + 1]);
+          if (OP == OP_RESID) {
+            const T r = bval - acc;
+            out = surf ? acc : r;
+            const bool counted = !surf && so < HT_OOB;
+            nsq += counted ? (double)r * (double)r : 0.0;
+          } else {
+            out = surf ? acc : fma(omega_invd, bval - acc, c);
+          }
+        }
+        bstore(out, ry, so);
       }
     }
 #pragma unroll
     for (int r = 0; r < J + 2; ++r) {
       xm[r] = xc[r];
       xc[r] = xp[r];
+      oc[r] = op[r];
     }
   }
   if (OP == OP_RESID) {

@@ -289,3 +289,39 @@ def test_solve_mixed_precision():
           f"error vs FP64 oracle {err:.2e}")
     assert st["converged"] and st["rel_res"] <= 1e-10
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("rows", [4, 8, 16])
+@pytest.mark.parametrize("name,level", [("jittered_288", 4), ("ref_tet", 6),
+                                        ("slab_3_11", 5)])
+def test_apply_every_tile_shape(name, level, rows):
+    """All stencil-kernel tile shapes (64 i x rows) give the oracle's result,
+    for both precisions and for residual and Jacobi epilogues."""
+    P = pair(name, level, level)
+    S = P.S(level)
+    N = S.mesh.num_vertices
+    x = fields.uniform_values(N, 21)
+    b = fields.uniform_values(N, 22)
+    for dt, code, tol in ((torch.float64, ht.HT_F64, FP64_TOL),
+                          (torch.float32, ht.HT_F32, 20 * FP32_TOL)):
+        P.m.set_tile_rows(level, code, rows)
+        assert P.m.tile_rows(level, code) == rows
+        xg, bg = P.to_gpu(level, x, dt), P.to_gpu(level, b, dt)
+        yg = torch.zeros_like(xg)
+        P.m.apply(level, xg, yg)
+        assert rel_err(P.from_gpu(level, yg), S.apply(x)) <= tol
+        P.m.residual(level, xg, bg, yg)
+        assert rel_err(P.from_gpu(level, yg), S.residual(x, b)) <= tol
+        P.m.smooth_jacobi(level, xg, bg, 2.0 / 3.0, 1)
+        assert rel_err(P.from_gpu(level, xg), S.jacobi(x, b, 2.0 / 3.0, 1)) <= tol
+        P.m.set_tile_rows(level, code, 8)
+
+
+def test_autotune_picks_a_valid_shape(tmp_path):
+    P = pair("jittered_288", 4, 4)
+    cache = str(tmp_path / "tune.txt")
+    rows = P.m.autotune(4, ht.HT_F64, cache)
+    assert rows in (4, 8, 16) and P.m.tile_rows(4, ht.HT_F64) == rows
+    P.m.set_tile_rows(4, ht.HT_F64, 4 if rows != 4 else 8)
+    assert P.m.autotune(4, ht.HT_F64, cache) == rows      # from the cache
+    assert open(cache).read().count("\n") == 1
