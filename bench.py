@@ -138,11 +138,19 @@ def main():
     log(f"cell kernel {cell_avg:.3f} ms ({achieved:.0f} GB/s algorithmic), "
         f"exchange {exch_avg:.3f} ms")
 
-    if args.copy_calibration:
-        log(f"plain copy calibration: {nslot * 8} bytes read + written per copy")
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
+    # streaming-copy reference: one level vector read + written (known bytes)
+    copy_bytes = 2 * nslot * 8
+    reps = 3 if args.copy_calibration else 10
+    mesh.copy(L, x, y)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        mesh.copy(L, x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / reps
+    copy_gbs = copy_bytes / (copy_ms * 1e-3) / 1e9
+    log(f"plain copy of {nslot * 8} B: {copy_ms:.3f} ms, {copy_gbs:.0f} GB/s")
 
     # ---------------- FP32 apply ------------------------------------------
     x32, y32 = x.float(), torch.zeros(nslot, dtype=torch.float32, device=dev)
@@ -182,6 +190,8 @@ def main():
                      "kernel": f"k_cell<double, apply, {rows64}>",
                      "bytes_per_launch": BYTES_PER_DOF_F64 * ndof},
         "apply_hbm_frac": round(gdofs * BYTES_PER_DOF_F64 / HBM_PEAK_GBS, 4),
+        "stream_copy": {"ms": round(copy_ms, 4), "gbs": round(copy_gbs, 1),
+                        "bytes": copy_bytes, "kernel": "k_flat<double, double, copy>"},
         "tile_rows": {"f64": rows64, "f32": rows32},
         "kernel_ms": {"cell_apply": round(cell_avg, 4),
                       "exchange": round(exch_avg, 4)},
@@ -218,6 +228,24 @@ def main():
                 solves[name]["rel_diff_vs_f64"] = mesh.norm(L, diff) / mesh.norm(L, u64)
             log(f"solve {name}: {st['cycles']} cycles, {st['seconds']:.3f} s, "
                 f"rel res {st['rel_res']:.2e}")
+        # per-kernel device time of one eager FP64 and one mixed solve
+        breakdown = {}
+        for name, prec in (("f64", ht.HT_PREC_F64), ("mixed", ht.HT_PREC_MIXED)):
+            u = torch.zeros_like(b)
+            mesh.profile(True)
+            mesh.profile_reset()
+            mesh.solve(L, u, b, prec, 1e-10, 100, use_graph=False)
+            parts = {}
+            for kname in ("cell_apply", "cell_residual", "cell_jacobi", "exchange",
+                          "restrict", "prolongate", "zero_guess", "coarse_solve",
+                          "flat", "norm_sum", "dot"):
+                ms_k, cnt = mesh.profile_query(kname)
+                if cnt:
+                    parts[kname] = {"ms": round(ms_k, 2), "launches": cnt}
+            mesh.profile(False)
+            breakdown[name] = parts
+        log(f"solve kernel breakdown: {json.dumps(breakdown)}")
+        solves["kernel_ms"] = breakdown
         out["solve_to_1e-10"] = solves
 
     if not args.no_cpu:

@@ -165,6 +165,10 @@ int ht_norm(ht_mesh* mesh, int level, int dtype, const void* v, double* norm,
 int ht_dot(ht_mesh* mesh, int level, int dtype, const void* a, const void* b,
            double* dot, ht_stream stream);
 
+/* dst = src over all n_slots slots (a plain streaming copy). */
+int ht_copy(ht_mesh* mesh, int level, int dtype, const void* src, void* dst,
+            ht_stream stream);
+
 /* ------------------------------------------------------------ operators - */
 /* y = A x: the P1 Laplacian row sum_j a_ij x_j at every non-Dirichlet
  * micro-vertex (Section 5.2.2), y = 0 at Dirichlet ones.  x and y must not

@@ -160,6 +160,11 @@ class Mesh:
                             C.byref(r), _stream()))
         return r.value
 
+    def copy(self, level: int, src, dst):
+        check(load().ht_copy(self._h, level, _dtype_code(src), _ptr(src),
+                             _ptr(dst), _stream()))
+        return dst
+
     def apply(self, level: int, x, y):
         check(load().ht_apply(self._h, level, _dtype_code(x), _ptr(x), _ptr(y),
                               _stream()))

@@ -64,6 +64,7 @@ SIGNATURES = {
     "ht_lumped_mass": (I, [P, I, I, P, P]),
     "ht_norm": (I, [P, I, I, P, C.POINTER(D), P]),
     "ht_dot": (I, [P, I, I, P, P, C.POINTER(D), P]),
+    "ht_copy": (I, [P, I, I, P, P, P]),
     "ht_apply": (I, [P, I, I, P, P, P]),
     "ht_residual": (I, [P, I, I, P, P, P, C.POINTER(D), P]),
     "ht_smooth_jacobi": (I, [P, I, I, D, I, P, P, P]),

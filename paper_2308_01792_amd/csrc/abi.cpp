@@ -17,6 +17,8 @@ struct ht_mesh {
   ht::Mesh m;
   // (level, J) -> tile list on the device
   std::map<std::pair<int, int>, std::pair<int2*, int64_t>> tiles;
+  // level -> walk tiles (64 i x 8 rows) for the transfer / elementwise kernels
+  std::map<int, std::pair<int2*, int64_t>> walk_tiles;
   std::map<std::pair<int, int>, int> tuned_J;  // (level, dtype) -> J
   bool capturing = false;
 };
@@ -91,10 +93,19 @@ static T* upload(const std::vector<T>& v) {
 
 static const int kJ[] = {4, 8, 16};
 
+// Tile groups of the stencil kernel: 62 output i x (4 waves x J rows).
 static std::vector<int2> make_tiles(int n, int J) {
   std::vector<int2> t;
-  for (int tj = 0; J * tj <= n; ++tj)
-    for (int ti = 0; 62 * ti + J * tj <= n; ++ti) t.push_back(make_int2(62 * ti, J * tj));
+  const int G = 4 * J;
+  for (int tj = 0; G * tj <= n; ++tj)
+    for (int ti = 0; 62 * ti + G * tj <= n; ++ti) t.push_back(make_int2(62 * ti, G * tj));
+  return t;
+}
+
+static std::vector<int2> make_walk_tiles(int n) {
+  std::vector<int2> t;
+  for (int tj = 0; 8 * tj <= n; ++tj)
+    for (int ti = 0; 64 * ti + 8 * tj <= n; ++ti) t.push_back(make_int2(64 * ti, 8 * tj));
   return t;
 }
 
@@ -102,11 +113,11 @@ static int64_t partials_needed(const ht_mesh* h, int level) {
   const Mesh& m = h->m;
   const int n = 1 << level;
   int64_t cell_blocks = 0;
-  for (int J : kJ) cell_blocks = std::max<int64_t>(cell_blocks, m.nc * (int64_t)make_tiles(n, J).size());
+  for (int J : kJ) cell_blocks = std::max<int64_t>(cell_blocks, 4 * m.nc * (int64_t)make_tiles(n, J).size());
   const int64_t fp = n_tri(n - 2), total = m.n_faces * fp + m.n_edges * std::max(n - 1, 0) + m.n_verts;
   const int64_t exch_blocks = (total + 255) / 256;
-  const int64_t elem_blocks = m.nc * n_tri(n + 1);
-  return std::max(cell_blocks + exch_blocks, elem_blocks) + 64;
+  const int64_t elem_blocks = m.nc * (int64_t)make_walk_tiles(n).size();
+  return std::max(cell_blocks + exch_blocks, elem_blocks) + 512;
 }
 
 void ensure_uploaded_h(ht_mesh* h) {
@@ -164,6 +175,10 @@ void ensure_uploaded_h(ht_mesh* h) {
     for (int J : kJ) {
       auto t = make_tiles(1 << l, J);
       h->tiles[{l, J}] = {upload(t), (int64_t)t.size()};
+    }
+    {
+      auto t = make_walk_tiles(1 << l);
+      h->walk_tiles[l] = {upload(t), (int64_t)t.size()};
     }
     pcap = std::max(pcap, partials_needed(h, l));
   }
@@ -265,15 +280,17 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
     check_launch();
   }
   ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
-                          m.d_partials + ca.nblocks);
+                          m.d_partials + 4 * ca.nblocks);
   if (op == OP_RESID) ea.u = x;
+  ea.x = x;
+  ea.w = ca.w;
   {
     Prof p(h, "exchange", s);
     launch_exchange(dtype, op, ea, s);
     check_launch();
   }
   if (op == OP_RESID && want_norm) {
-    const int64_t cnt = ca.nblocks + (ea.total + 255) / 256;
+    const int64_t cnt = 4 * ca.nblocks + (ea.total + 255) / 256;
     Prof p(h, "norm_sum", s);
     launch_sum_partials(m.d_partials, cnt, m.d_scalar + scalar_slot, true, s);
     check_launch();
@@ -301,6 +318,10 @@ static ElemArgs elem_args(ht_mesh* h, int level) {
   a.n = L.n;
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
   a.nscale = (double)L.n;
+  auto& t = h->walk_tiles.at(level);
+  a.tiles = t.first;
+  a.ntiles = t.second;
+  a.nblocks = m.nc * t.second;
   return a;
 }
 
@@ -324,15 +345,15 @@ static void zero_guess_sweep(ht_mesh* h, int level, int dtype, double omega,
 static void restrict_pass(ht_mesh* h, int fine, int dtype, const void* rf,
                           void* rc, hipStream_t s) {
   Mesh& m = h->m;
-  const CellLayout Lf = make_layout(fine), Lc = make_layout(fine - 1);
-  XferArgs a{};
-  a.src = rf; a.dst = rc; a.cls = m.d_cls; a.ncells = m.nc;
-  a.nf = Lf.n; a.nc_ = Lc.n;
-  a.stride_f = Lf.stride; a.off_s0_f = Lf.off_s0; a.off_s1_f = Lf.off_s1;
-  a.stride_c = Lc.stride; a.off_s0_c = Lc.off_s0; a.off_s1_c = Lc.off_s1;
+  const CellLayout Lc = make_layout(fine - 1);
+  const int J = choose_J(h, fine, dtype);
+  CellArgs ca = cell_args(h, fine, dtype, J, rf, rc, nullptr, 0.0);
+  ca.stride_out = Lc.stride;
+  ca.off_s0_out = Lc.off_s0;
+  ca.off_s1_out = Lc.off_s1;
   {
     Prof p(h, "restrict", s);
-    launch_restrict(dtype, a, s);
+    launch_cell(dtype, OP_RESTRICT, J, ca, s);
     check_launch();
   }
   ExchArgs ea = exch_args(h, fine - 1, rc, nullptr, nullptr, 0.0, m.d_partials);
@@ -350,6 +371,10 @@ static void prolong_pass(ht_mesh* h, int coarse, int dtype, const void* ec,
   a.nf = Lf.n; a.nc_ = Lc.n;
   a.stride_f = Lf.stride; a.off_s0_f = Lf.off_s0; a.off_s1_f = Lf.off_s1;
   a.stride_c = Lc.stride; a.off_s0_c = Lc.off_s0; a.off_s1_c = Lc.off_s1;
+  {
+    auto& t = h->walk_tiles.at(coarse + 1);
+    a.tiles = t.first; a.ntiles = t.second; a.nblocks = m.nc * t.second;
+  }
   Prof p(h, "prolongate", s);
   launch_prolong(dtype, a, s);
   check_launch();
@@ -467,8 +492,7 @@ static double norm_of(ht_mesh* h, int level, int dtype, const void* a,
     launch_elem(dtype, EOP_DOT, ea, s);
     check_launch();
   }
-  const int64_t cnt = h->m.nc * n_tri(make_layout(level).n + 1);
-  launch_sum_partials(h->m.d_partials, cnt, h->m.d_scalar + 1, sq, s);
+  launch_sum_partials(h->m.d_partials, ea.nblocks, h->m.d_scalar + 1, sq, s);
   check_launch();
   return read_scalar(h, 1, s);
 }
@@ -533,6 +557,7 @@ int ht_mesh_destroy(ht_mesh* h) {
       (void)hipDeviceSynchronize();
       for (auto& kv : m.graphs) (void)hipGraphExecDestroy(kv.second.exec);
       for (auto& kv : h->tiles) (void)hipFree(kv.second.first);
+      for (auto& kv : h->walk_tiles) (void)hipFree(kv.second.first);
       for (auto* p : m.d_w64) if (p) (void)hipFree(p);
       for (auto* p : m.d_w32) if (p) (void)hipFree(p);
       for (auto* list : {&m.work64, &m.work32})
@@ -719,6 +744,16 @@ int ht_dot(ht_mesh* h, int level, int dtype, const void* a, const void* b,
     check_ptr(b, "b");
     if (!dot) throw Error{HT_ERR_ARG, "dot is NULL"};
     *dot = norm_of(h, level, dtype, a, b, s, false);
+  });
+}
+
+int ht_copy(ht_mesh* h, int level, int dtype, const void* src, void* dst,
+            ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(src, "src");
+    check_ptr(dst, "dst");
+    flat(h, level, dtype, dtype, FOP_COPY, dst, src, s);
   });
 }
 

@@ -17,13 +17,13 @@ namespace ht {
 
 // ------------------------------------------------------- lane exchange --
 // DPP wave shifts (GFX9 family): wave_shr:1 gives lane L the value of lane
-// L-1, wave_shl:1 the value of lane L+1.  Lanes shifted in from outside the
-// wave read 0.
+// L-1, wave_shl:1 the value of lane L+1.  With bound_ctrl set, lanes shifted
+// in from outside the wave read 0 and no "old" value has to be materialised.
 __device__ __forceinline__ int dpp_prev(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int dpp_next(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);
 }
 __device__ __forceinline__ float lane_prev(float v) {
   return __int_as_float(dpp_prev(__float_as_int(v)));
@@ -121,47 +121,71 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r,
 
 // One wave = one tile of 64 consecutive i (62 outputs, one halo lane on each
 // side) and J rows j0..j0+J-1, marching k upwards with the planes k-1, k,
-// k+1 of rows j0-1..j0+J in registers; i +- 1 neighbours come from DPP.
+// k+1 of rows j0-1..j0+J in registers; i +- 1 neighbours come from DPP.  The
+// loads of plane k+2 are issued before plane k is computed, so memory
+// latency overlaps one plane of arithmetic.
 //
 // Points on the cell's faces get the cell's partial row.  On rows with
-// j >= 1, k >= 1 and line end e >= 2 only two lanes can be surface points:
-// i = 0 (face i = 0) and i = e (slanted face).  Their partial row equals the
-// interior row (values outside the closure load as 0) plus a 7-term
-// correction over the in-face offsets with uniform weights.  Rows with
-// j == 0, k == 0 or e <= 1 take per-lane class weights from LDS.
+// j >= 1, k >= 1 and line end e >= 2 ("generic" rows) only two lanes are
+// surface points: i = 0 (face i = 0) and i = e (slanted face).  They store
+// the interior formula evaluated with zero outside the closure; the cell's
+// exact partial row differs from it by a 7-term sum over the in-face offsets
+// only, which the ghost-exchange kernel adds.  Rows with j == 0, k == 0 or
+// e <= 1 take exact per-lane class weights from LDS.
+//
+// OP_RESTRICT runs the same march over a fine residual with the fixed
+// stencil of P^T (1 at the centre, 1/2 on the 14 edge neighbours) and
+// evaluates it at even (i, j, k) only, writing the coarse point (i,j,k)/2.
+// Fine points this cell does not own (or Dirichlet points) read as zero, so
+// every fine micro-vertex is restricted by exactly one cell and shared coarse
+// points receive partial sums for the ghost exchange.
 template <typename T, int OP, int J>
-__global__ __launch_bounds__(64) void k_cell(CellArgs a) {
+__global__ __launch_bounds__(256) void k_cell(CellArgs a) {
+  constexpr bool RESTR = (OP == OP_RESTRICT);
   __shared__ T wtab[16 * 15];
-  __shared__ T wdel[14];  // in-face corrections: face i = 0, slanted face
-  const int lane = threadIdx.x;
+  // A workgroup is four waves on four vertically adjacent tiles of one cell
+  // (rows j0 .. j0 + 4J - 1): the waves march in near lockstep on one CU,
+  // so each wave's halo rows are its neighbours' rows, fetched once.
   // XCD-aware block order: block b runs on XCD b % 8; give each XCD a
-  // contiguous run of (cell, tile) work so tiles sharing halo rows share L2.
+  // contiguous run of (cell, tile group) work so neighbouring groups share
+  // an L2.
   const int64_t nb = a.nblocks;
   const int64_t chunk = (nb + 7) / 8;
-  const int64_t w = (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
-  if (w >= nb) return;
-  const int64_t cell = w / a.ntiles;
-  const int2 tile = a.tiles[w % a.ntiles];
-  const int i0 = tile.x, j0 = tile.y;
+  const int64_t wb = (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
+  if (wb >= nb) return;
+  const int64_t cell = wb / a.ntiles;
+  const int2 tile = a.tiles[wb % a.ntiles];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t w = wb * 4 + wave;  // partial-sum slot of this wave
+  const int i0 = tile.x, j0 = tile.y + wave * J;
   const int n = a.n;
   const int64_t bytes = a.stride * (int64_t)sizeof(T);
+  const int64_t ostride = RESTR ? a.stride_out : a.stride;
   const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
-  const __amdgpu_buffer_rsrc_t ry = make_rsrc((T*)a.y + cell * a.stride, bytes);
+  const __amdgpu_buffer_rsrc_t ry =
+      make_rsrc((T*)a.y + cell * ostride, ostride * (int64_t)sizeof(T));
   const __amdgpu_buffer_rsrc_t rb =
       make_rsrc(a.b ? (const T*)a.b + cell * a.stride : (const T*)a.y, bytes);
-  const T* wc = (const T*)a.w + cell * 240;
-  for (int t = lane; t < 240; t += 64) wtab[t] = wc[t];
-  if (lane < 14) {
-    const int d0[7] = {0, 3, 4, 5, 6, 11, 12}, d8[7] = {0, 7, 8, 9, 10, 11, 12};
-    const int d = lane < 7 ? d0[lane] : d8[lane - 7];
-    const int cls = lane < 7 ? 1 : 8;
-    wdel[lane] = wc[cls * 15 + d] - wc[d];
+  T w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, w6 = 0, w7 = 0, w8 = 0,
+    w9 = 0, w10 = 0, w11 = 0, w12 = 0, w13 = 0, w14 = 0;
+  unsigned own16 = 0;
+  if (!RESTR) {
+    const T* wc = (const T*)a.w + cell * 240;
+    for (int t = threadIdx.x; t < 240; t += 256) wtab[t] = wc[t];
+    __syncthreads();
+    // interior weights from LDS: they stay in VGPRs and leave the scalar
+    // registers to the row bookkeeping
+    w0 = wtab[0]; w1 = wtab[1]; w2 = wtab[2]; w3 = wtab[3]; w4 = wtab[4];
+    w5 = wtab[5]; w6 = wtab[6]; w7 = wtab[7]; w8 = wtab[8]; w9 = wtab[9];
+    w10 = wtab[10]; w11 = wtab[11]; w12 = wtab[12]; w13 = wtab[13];
+    w14 = wtab[14];
+  } else {
+    const uint8_t fl = lane < 16 ? a.cls[cell * 16 + lane].flags : 0;
+    own16 = (unsigned)__ballot((fl & kClsOwner) && !(fl & kClsDirichlet)) & 0xffffu;
   }
-  __syncthreads();
-  const T w0 = wc[0], w1 = wc[1], w2 = wc[2], w3 = wc[3], w4 = wc[4],
-          w5 = wc[5], w6 = wc[6], w7 = wc[7], w8 = wc[8], w9 = wc[9],
-          w10 = wc[10], w11 = wc[11], w12 = wc[12], w13 = wc[13], w14 = wc[14];
-  const T omega_invd = (T)(a.omega * a.nscale * a.cls[cell * 16].inv_diag_unit);
+  const T omega_invd =
+      RESTR ? (T)0 : (T)(a.omega * a.nscale * a.cls[cell * 16].inv_diag_unit);
   const int off_s0 = (int)a.off_s0, off_s1 = (int)a.off_s1;
 
   const int i = i0 - 1 + lane;
@@ -172,13 +196,13 @@ __global__ __launch_bounds__(64) void k_cell(CellArgs a) {
   // entries sa(j), sb(j); consecutive rows differ by the main-block row
   // length (n-1-kk-j) and by 1 in S0/S1.
   auto plane_offsets = [&](int kk, unsigned (&o)[J + 2]) {
-    const int w1 = n - 1;
-    int mb = (int)(n_tet(w1) - n_tet(w1 - kk)) - 1;
+    const int w1_ = n - 1;
+    int mb = (int)(n_tet(w1_) - n_tet(w1_ - kk)) - 1;
     int sa = off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - kk));
     int sb = off_s1 + (int)(n_tri(n) - n_tri(n - kk));
     const int jf = j0 - 1;
     if (jf > 0) {
-      mb += jf * (w1 - kk) - jf * (jf - 1) / 2;
+      mb += jf * (w1_ - kk) - jf * (jf - 1) / 2;
       sa += jf;
       sb += jf;
     }
@@ -194,103 +218,141 @@ __global__ __launch_bounds__(64) void k_cell(CellArgs a) {
       }
       o[r] = off;
       if (j >= 0) {
-        mb += w1 - kk - j;
+        mb += w1_ - kk - j;
         ++sa;
         ++sb;
       }
     }
   };
+  // restriction: fine points not owned by this cell read as zero
+  auto mask_plane = [&](int kk, T (&v)[J + 2]) {
+    if (RESTR) {
+#pragma unroll
+      for (int r = 0; r < J + 2; ++r) {
+        const int j = j0 - 1 + r;
+        const int cls = (int)is0 | ((j == 0) << 1) | ((kk == 0) << 2) | ((i == n - j - kk) << 3);
+        v[r] = ((own16 >> cls) & 1u) ? v[r] : (T)0;
+      }
+    }
+  };
 
-  T xm[J + 2], xc[J + 2], xp[J + 2];
-  unsigned oc[J + 2];
-  plane_offsets(0, oc);
-#pragma unroll
-  for (int r = 0; r < J + 2; ++r) {
-    xm[r] = (T)0;
-    bload(xc[r], rx, oc[r]);
-  }
+  constexpr bool NEED_B = (OP == OP_RESID || OP == OP_JACOBI);
   double nsq = 0.0;
-  const int kmax = n - i0 - j0;
-  for (int k = 0; k <= kmax; ++k) {
-    unsigned op[J + 2];
-    plane_offsets(k + 1, op);
+  // One plane step: compute plane k from (pm, pc, pp) = planes k-1, k, k+1
+  // while the loads of plane k+2 go into pn.  The k loop is unrolled by four
+  // so the four plane buffers rotate by renaming, not by register moves.
+  auto step = [&](int k, T (&pm)[J + 2], T (&pc)[J + 2], T (&pp)[J + 2],
+                  T (&pn)[J + 2], unsigned (&oc)[J + 2], unsigned (&op)[J + 2],
+                  unsigned (&on)[J + 2], T (&bc)[J], T (&bp)[J]) {
+    plane_offsets(k + 2, on);
 #pragma unroll
-    for (int r = 0; r < J + 2; ++r) bload(xp[r], rx, op[r]);
+    for (int r = 0; r < J + 2; ++r) bload(pn[r], rx, on[r]);
+    if (NEED_B) {
+#pragma unroll
+      for (int r = 0; r < J; ++r) bload(bp[r], rb, op[r + 1]);
+    }
+    mask_plane(k + 1, pp);
+    if (RESTR && (k & 1)) return;
 #pragma unroll
     for (int rr = 0; rr < J; ++rr) {
       const int j = j0 + rr;
       const int e = n - j - k;
-      if (e >= i0) {
-        const T c = xc[rr + 1];
-        const T v1 = lane_next(c), v2 = lane_prev(c);
-        const T v3 = xc[rr + 2], v4 = xc[rr];
-        const T v5 = xp[rr + 1], v6 = xm[rr + 1];
-        const T v7 = lane_prev(xc[rr + 2]), v8 = lane_next(xc[rr]);
-        const T v9 = lane_prev(xp[rr + 1]), v10 = lane_next(xm[rr + 1]);
-        const T v11 = xp[rr], v12 = xm[rr + 2];
-        const T v13 = lane_next(xp[rr]), v14 = lane_prev(xm[rr + 2]);
-        T acc = w0 * c;
-        acc = fma(w1, v1, acc); acc = fma(w2, v2, acc); acc = fma(w3, v3, acc);
-        acc = fma(w4, v4, acc); acc = fma(w5, v5, acc); acc = fma(w6, v6, acc);
-        acc = fma(w7, v7, acc); acc = fma(w8, v8, acc); acc = fma(w9, v9, acc);
-        acc = fma(w10, v10, acc); acc = fma(w11, v11, acc);
-        acc = fma(w12, v12, acc); acc = fma(w13, v13, acc);
-        acc = fma(w14, v14, acc);
-        bool surf;
-        if (j == 0 || k == 0 || e <= 1) {
-          const int cls = (int)is0 | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3);
-          const T* wt = wtab + cls * 15;
-          T sacc = wt[0] * c;
-          sacc = fma(wt[1], v1, sacc); sacc = fma(wt[2], v2, sacc);
-          sacc = fma(wt[3], v3, sacc); sacc = fma(wt[4], v4, sacc);
-          sacc = fma(wt[5], v5, sacc); sacc = fma(wt[6], v6, sacc);
-          sacc = fma(wt[7], v7, sacc); sacc = fma(wt[8], v8, sacc);
-          sacc = fma(wt[9], v9, sacc); sacc = fma(wt[10], v10, sacc);
-          sacc = fma(wt[11], v11, sacc); sacc = fma(wt[12], v12, sacc);
-          sacc = fma(wt[13], v13, sacc); sacc = fma(wt[14], v14, sacc);
-          acc = sacc;
-          surf = cls != 0;
-        } else {
-          const bool ise = (i == e);
-          if (i0 == 0) {  // face i = 0: class-1 minus interior weights
-            T cc = wdel[0] * c;
-            cc = fma(wdel[1], v3, cc); cc = fma(wdel[2], v4, cc);
-            cc = fma(wdel[3], v5, cc); cc = fma(wdel[4], v6, cc);
-            cc = fma(wdel[5], v11, cc); cc = fma(wdel[6], v12, cc);
-            acc = is0 ? acc + cc : acc;
-          }
-          if (e <= i0 + 61) {  // slanted face: class-8 minus interior weights
-            T cc = wdel[7] * c;
-            cc = fma(wdel[8], v7, cc); cc = fma(wdel[9], v8, cc);
-            cc = fma(wdel[10], v9, cc); cc = fma(wdel[11], v10, cc);
-            cc = fma(wdel[12], v11, cc); cc = fma(wdel[13], v12, cc);
-            acc = ise ? acc + cc : acc;
-          }
-          surf = is0 || ise;
-        }
-        const unsigned so = oc[rr + 1] | out_mask;
-        T out = acc;
-        if (OP == OP_RESID || OP == OP_JACOBI) {
-          T bval;
-          bload(bval, rb, oc[rr + 1]);
-          if (OP == OP_RESID) {
-            const T r = bval - acc;
-            out = surf ? acc : r;
-            const bool counted = !surf && so < HT_OOB;
-            nsq += counted ? (double)r * (double)r : 0.0;
-          } else {
-            out = surf ? acc : fma(omega_invd, bval - acc, c);
-          }
-        }
-        bstore(out, ry, so);
+      if (RESTR && (rr & 1)) continue;
+      if (e < i0) continue;
+      const T c = pc[rr + 1];
+      const T v1 = lane_next(c), v2 = lane_prev(c);
+      const T v3 = pc[rr + 2], v4 = pc[rr];
+      const T v5 = pp[rr + 1], v6 = pm[rr + 1];
+      const T v7 = lane_prev(pc[rr + 2]), v8 = lane_next(pc[rr]);
+      const T v9 = lane_prev(pp[rr + 1]), v10 = lane_next(pm[rr + 1]);
+      const T v11 = pp[rr], v12 = pm[rr + 2];
+      const T v13 = lane_next(pp[rr]), v14 = lane_prev(pm[rr + 2]);
+      if (RESTR) {
+        // P^T at the even fine point (i, j, k) -> coarse (i, j, k) / 2
+        const T nb14 = ((v1 + v2) + (v3 + v4)) + ((v5 + v6) + (v7 + v8)) +
+                       ((v9 + v10) + (v11 + v12)) + (v13 + v14);
+        const T val = fma((T)0.5, nb14, c);
+        const int nc = n >> 1, jc = j >> 1, kc = k >> 1, ec = nc - jc - kc;
+        const int mbc = (int)t_w(nc - 1, 0, jc, kc) - 1;
+        const int sac = (int)a.off_s0_out + (int)t2_w(nc + 1, jc, kc);
+        const int sbc = (int)a.off_s1_out + (int)t2_w(nc, jc, kc);
+        const int ic = i >> 1;
+        int el = (ic == ec) ? sbc : mbc + ic;
+        el = (ic == 0) ? sac : el;
+        const bool ok = ((i & 1) == 0) && out_mask == 0u && i >= 0 && i <= e;
+        bstore(val, ry, ok ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB);
+        continue;
       }
+      T acc = w0 * c;
+      acc = fma(w1, v1, acc); acc = fma(w2, v2, acc); acc = fma(w3, v3, acc);
+      acc = fma(w4, v4, acc); acc = fma(w5, v5, acc); acc = fma(w6, v6, acc);
+      acc = fma(w7, v7, acc); acc = fma(w8, v8, acc); acc = fma(w9, v9, acc);
+      acc = fma(w10, v10, acc); acc = fma(w11, v11, acc);
+      acc = fma(w12, v12, acc); acc = fma(w13, v13, acc);
+      acc = fma(w14, v14, acc);
+      bool surf;
+      if (j == 0 || k == 0 || e <= 1) {
+        const int cls = (int)is0 | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3);
+        const T* wt = wtab + cls * 15;
+        T sacc = wt[0] * c;
+        sacc = fma(wt[1], v1, sacc); sacc = fma(wt[2], v2, sacc);
+        sacc = fma(wt[3], v3, sacc); sacc = fma(wt[4], v4, sacc);
+        sacc = fma(wt[5], v5, sacc); sacc = fma(wt[6], v6, sacc);
+        sacc = fma(wt[7], v7, sacc); sacc = fma(wt[8], v8, sacc);
+        sacc = fma(wt[9], v9, sacc); sacc = fma(wt[10], v10, sacc);
+        sacc = fma(wt[11], v11, sacc); sacc = fma(wt[12], v12, sacc);
+        sacc = fma(wt[13], v13, sacc); sacc = fma(wt[14], v14, sacc);
+        acc = sacc;
+        surf = cls != 0;
+      } else {
+        // generic row: the lanes i = 0 and i = e hold the cell's interior
+        // formula with zero outside the closure; the ghost exchange adds
+        // their in-face correction.
+        surf = is0 || (i == e);
+      }
+      const unsigned so = oc[rr + 1] | out_mask;
+      T out = acc;
+      if (NEED_B) {
+        const T bval = bc[rr];
+        if (OP == OP_RESID) {
+          const T r = bval - acc;
+          out = surf ? acc : r;
+          const bool counted = !surf && so < HT_OOB;
+          nsq += counted ? (double)r * (double)r : 0.0;
+        } else {
+          out = surf ? acc : fma(omega_invd, bval - acc, c);
+        }
+      }
+      bstore(out, ry, so);
     }
+  };
+
+  T PA[J + 2], PB[J + 2], PC[J + 2], PD[J + 2];
+  unsigned OA[J + 2], OB[J + 2], OC[J + 2], OD[J + 2];
+  T BA[J], BB[J];
+  plane_offsets(0, OB);
+  plane_offsets(1, OC);
 #pragma unroll
-    for (int r = 0; r < J + 2; ++r) {
-      xm[r] = xc[r];
-      xc[r] = xp[r];
-      oc[r] = op[r];
-    }
+  for (int r = 0; r < J + 2; ++r) {
+    PA[r] = (T)0;
+    OA[r] = HT_OOB;
+    bload(PB[r], rx, OB[r]);
+    bload(PC[r], rx, OC[r]);
+  }
+  if (NEED_B) {
+#pragma unroll
+    for (int r = 0; r < J; ++r) bload(BA[r], rb, OB[r + 1]);
+  }
+  mask_plane(0, PB);
+  const int kmax = n - i0 - j0;
+  for (int k = 0; k <= kmax; k += 4) {
+    step(k, PA, PB, PC, PD, OB, OC, OD, BA, BB);
+    if (k + 1 > kmax) break;
+    step(k + 1, PB, PC, PD, PA, OC, OD, OA, BB, BA);
+    if (k + 2 > kmax) break;
+    step(k + 2, PC, PD, PA, PB, OD, OA, OB, BA, BB);
+    if (k + 3 > kmax) break;
+    step(k + 3, PD, PA, PB, PC, OA, OB, OC, BB, BA);
   }
   if (OP == OP_RESID) {
     nsq = wave_sum(nsq);
@@ -311,6 +373,14 @@ __device__ __forceinline__ void tri_decode(int64_t p, int m, int& a, int& b) {
   a = (int)(p - start(bb));
 }
 
+// In-face offsets of the face i = 0 (class 1) and of the slanted face
+// i + j + k = n (class 8), as indices into the 15-offset list.
+__constant__ int kInFace1[7] = {0, 3, 4, 5, 6, 11, 12};
+__constant__ int kInFace8[7] = {0, 7, 8, 9, 10, 11, 12};
+
+// One thread per micro-vertex shared by several cells (face interiors, then
+// edge interiors, then vertices).  Sums the partial rows of all incident
+// cells in cell order, applies the epilogue of OP and writes every copy.
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -340,14 +410,20 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
     }
     const DevPrim P = a.prim[prim];
     const int cnt = P.inc_count;
-    // slot of this point in the closure of the q-th incident cell
-    auto slot_q = [&](int q) -> int64_t {
+    // local index of this point in the q-th incident cell
+    auto local_q = [&](int q, int& i, int& j, int& k) {
       const DevInc I = a.inc[P.inc_begin + q];
       int w[4] = {0, 0, 0, 0};
       w[I.lv[0]] = gw[0];
       if (I.lv[1] >= 0) w[I.lv[1]] = gw[1];
       if (I.lv[2] >= 0) w[I.lv[2]] = gw[2];
-      return (int64_t)I.cell * L.stride + slot_of(L, w[1], w[2], w[3]);
+      i = w[1]; j = w[2]; k = w[3];
+      return I;
+    };
+    auto slot_q = [&](int q) -> int64_t {
+      int i, j, k;
+      const DevInc I = local_q(q, i, j, k);
+      return (int64_t)I.cell * L.stride + slot_of(L, i, j, k);
     };
     T* y = (T*)a.y;
     const int64_t s0 = slot_q(0);
@@ -359,8 +435,32 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
         for (int q = 0; q < cnt; ++q) y[slot_q(q)] = (T)a.fill;
     } else {
       // partial rows of the incident cells, summed in cell order
-      T sum = y[s0];
-      for (int q = 1; q < cnt; ++q) sum += y[slot_q(q)];
+      T sum = (T)0;
+      for (int q = 0; q < cnt; ++q) {
+        int i, j, k;
+        const DevInc I = local_q(q, i, j, k);
+        const int64_t cb = (int64_t)I.cell * L.stride;
+        sum += y[cb + slot_of(L, i, j, k)];
+        // The stencil kernel left the interior formula at face points of
+        // faces i = 0 / i+j+k = n on its generic rows (e >= 2): add the
+        // in-face part of (class weights - interior weights) . x.
+        const bool gen1 = I.cls == 1 && n - j - k >= 2;
+        const bool gen8 = I.cls == 8 && i >= 2;
+        if ((OP == OP_APPLY || OP == OP_RESID || OP == OP_JACOBI) && (gen1 || gen8)) {
+          const T* wc = (const T*)a.w + (int64_t)I.cell * 240;
+          const T* xc = (const T*)a.x + cb;
+          const int* dl = gen1 ? kInFace1 : kInFace8;
+          T corr = (T)0;
+#pragma unroll
+          for (int m = 0; m < 7; ++m) {
+            int di, dj, dk;
+            stencil_offset(dl[m], di, dj, dk);
+            const T dw = wc[I.cls * 15 + dl[m]] - wc[dl[m]];
+            corr += dw * xc[slot_of(L, i + di, j + dj, k + dk)];
+          }
+          sum += corr;
+        }
+      }
       T val;
       if (P.boundary) {
         val = (OP == OP_JACOBI) ? ((const T*)a.u)[s0] : (T)0;
@@ -387,138 +487,253 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
   }
 }
 
-// ----------------------------------------------------- per-row kernels --
-// Grid: x = closure row (k outer, j inner) of a cell, y = cell.  Threads run
-// along i.  Used by transfers and elementwise kernels.
-__device__ __forceinline__ bool decode_row(int n, int r, int& j, int& k) {
-  int base = 0;
-  for (k = 0; k <= n; ++k) {
-    const int rows = n + 1 - k;
-    if (r < base + rows) { j = r - base; return true; }
-    base += rows;
+// --------------------------------------------------------- tile walker --
+// Visits the closure points of one (cell, tile): lanes are 64 consecutive
+// i = i0 + lane, rows j0 .. j0 + kWalkRows - 1, planes k = 0 .. n - i0 - j0.
+// f(i, j, k, e, el) gets the line end e = n - j - k and the element offset
+// el of the point inside its cell block (closure layout of index.hpp).
+enum { kWalkRows = 8 };
+template <typename F>
+__device__ __forceinline__ void walk_tile(const Lay& L, int i0, int j0, int i,
+                                          F&& f) {
+  const int n = L.n, w1 = n - 1;
+  const int kmax = n - i0 - j0;
+  for (int k = 0; k <= kmax; ++k) {
+    int mb = (int)(n_tet(w1) - n_tet(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
+    int sa = (int)L.off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - k)) + j0;
+    int sb = (int)L.off_s1 + (int)(n_tri(n) - n_tri(n - k)) + j0;
+#pragma unroll
+    for (int r = 0; r < kWalkRows; ++r) {
+      const int j = j0 + r;
+      const int e = n - j - k;
+      if (e < i0) break;
+      if (i <= e) f(i, j, k, e, i == 0 ? sa : (i == e ? sb : mb + i));
+      mb += w1 - k - j;
+      ++sa;
+      ++sb;
+    }
   }
-  return false;
 }
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_restrict(XferArgs a) {
-  const Lay Lf{a.nf, a.stride_f, a.off_s0_f, a.off_s1_f};
-  const Lay Lc{a.nc_, a.stride_c, a.off_s0_c, a.off_s1_c};
-  int j, k;
-  if (!decode_row(Lc.n, blockIdx.x, j, k)) return;
-  const int64_t cell = blockIdx.y;
-  const T* rf = (const T*)a.src + cell * Lf.stride;
-  T* rc = (T*)a.dst + cell * Lc.stride;
-  const ClassInfo* ci = a.cls + cell * 16;
-  const int e = Lc.n - j - k;
-  for (int i = threadIdx.x; i <= e; i += 64) {
-    const int F0 = 2 * i, F1 = 2 * j, F2 = 2 * k;
-    T s = (T)0;
-#pragma unroll
-    for (int d = 0; d < 15; ++d) {
-      int di, dj, dk;
-      stencil_offset(d, di, dj, dk);
-      const int fi = F0 + di, fj = F1 + dj, fk = F2 + dk;
-      if (fi < 0 || fj < 0 || fk < 0 || fi + fj + fk > Lf.n) continue;
-      const int cls = point_class(Lf.n, fi, fj, fk);
-      const uint8_t fl = ci[cls].flags;
-      if (!(fl & kClsOwner) || (fl & kClsDirichlet)) continue;
-      const T v = rf[slot_of(Lf, fi, fj, fk)];
-      s += d == 0 ? v : (T)0.5 * v;
-    }
-    rc[slot_of(Lc, i, j, k)] = s;
-  }
+// Block -> (cell, tile) with the XCD-aware order of the stencil kernel.
+__device__ __forceinline__ bool walk_block(int64_t nblocks, int64_t ntiles,
+                                           const int2* tiles, int64_t& cell,
+                                           int& i0, int& j0, int64_t& w) {
+  const int64_t chunk = (nblocks + 7) / 8;
+  w = (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
+  if (w >= nblocks) return false;
+  cell = w / ntiles;
+  const int2 t = tiles[w % ntiles];
+  i0 = t.x;
+  j0 = t.y;
+  return true;
+}
+
+// Prolongation u_f += P e_c, fine walk: a fine point with even index copies
+// the coarse value at half its index; otherwise it is the midpoint of the
+// coarse micro-edge along the one direction d with the same parity, and
+// takes the mean of the coarse values at (f - d)/2 and (f + d)/2 (for even
+// points both parents coincide and the mean is exact).  Coarse Dirichlet
+// values count as zero.  The coarse rows of the parents only depend on the
+// lane parity, so their bases are computed once per row (scalar).
+struct CRow {
+  int mb, sa, sb, e;
+};
+__device__ __forceinline__ CRow crow(const Lay& L, int j, int k) {
+  const int n = L.n;
+  CRow r;
+  r.e = n - j - k;
+  r.mb = (int)t_w(n - 1, 0, j, k) - 1;
+  r.sa = (int)L.off_s0 + (int)t2_w(n + 1, j, k);
+  r.sb = (int)L.off_s1 + (int)t2_w(n, j, k);
+  return r;
+}
+__device__ __forceinline__ void parity_dir(int p, int& di, int& dj, int& dk) {
+  // direction with parity p among x, y, xy, z, xz, yz, xyz (0 for p = 0)
+  di = (p == 1 || p == 7) ? 1 : ((p == 3 || p == 5) ? -1 : 0);
+  dj = (p == 2 || p == 3) ? 1 : ((p == 6 || p == 7) ? -1 : 0);
+  dk = (p >= 4) ? 1 : 0;
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_prolong(XferArgs a) {
+  int64_t cell, w;
+  int i0, j0;
+  if (!walk_block(a.nblocks, a.ntiles, a.tiles, cell, i0, j0, w)) return;
+  const int lane = threadIdx.x;
+  const uint8_t fl = lane < 16 ? a.cls[cell * 16 + lane].flags : 0;
+  const unsigned dmask = (unsigned)__ballot((fl & kClsDirichlet) != 0) & 0xffffu;
   const Lay Lf{a.nf, a.stride_f, a.off_s0_f, a.off_s1_f};
   const Lay Lc{a.nc_, a.stride_c, a.off_s0_c, a.off_s1_c};
-  int j, k;
-  if (!decode_row(Lf.n, blockIdx.x, j, k)) return;
-  const int64_t cell = blockIdx.y;
-  const T* ec = (const T*)a.src + cell * Lc.stride;
-  T* uf = (T*)a.dst + cell * Lf.stride;
-  const ClassInfo* ci = a.cls + cell * 16;
-  // direction with parity p (bits i, j, k) among the seven edge directions
-  const signed char dir[8][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0}, {-1, 1, 0},
-                                 {0, 0, 1},  {-1, 0, 1}, {0, -1, 1}, {1, -1, 1}};
-  const int e = Lf.n - j - k;
-  auto coarse = [&](int ci_, int cj, int ck) -> T {
-    const int cls = point_class(Lc.n, ci_, cj, ck);
-    if (ci[cls].flags & kClsDirichlet) return (T)0;
-    return ec[slot_of(Lc, ci_, cj, ck)];
-  };
-  for (int i = threadIdx.x; i <= e; i += 64) {
-    const int cls = point_class(Lf.n, i, j, k);
-    if (ci[cls].flags & kClsDirichlet) continue;
-    const int p = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
-    T v;
-    if (p == 0) {
-      v = coarse(i >> 1, j >> 1, k >> 1);
-    } else {
-      const int di = dir[p][0], dj = dir[p][1], dk = dir[p][2];
-      v = (T)0.5 * (coarse((i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1) +
-                    coarse((i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1));
+  const __amdgpu_buffer_rsrc_t rc =
+      make_rsrc((const T*)a.src + cell * Lc.stride, Lc.stride * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t ru =
+      make_rsrc((T*)a.dst + cell * Lf.stride, Lf.stride * (int64_t)sizeof(T));
+  const int n = Lf.n, w1 = n - 1, i = i0 + lane;
+  const bool odd = (i & 1) != 0;
+  const int kmax = n - i0 - j0;
+  for (int k = 0; k <= kmax; ++k) {
+    // all loads of the plane's rows first, then the updates
+    unsigned ou[kWalkRows], oa[kWalkRows], ob[kWalkRows];
+    bool za[kWalkRows], zb[kWalkRows];
+    int mb = (int)(n_tet(w1) - n_tet(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
+    int sa = (int)Lf.off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - k)) + j0;
+    int sb = (int)Lf.off_s1 + (int)(n_tri(n) - n_tri(n - k)) + j0;
+#pragma unroll
+    for (int r = 0; r < kWalkRows; ++r) {
+      const int j = j0 + r;
+      const int e = n - j - k;
+      const bool valid = e >= i0 && i <= e;
+      const int el = i == 0 ? sa : (i == e ? sb : mb + i);
+      ou[r] = valid ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB;
+      mb += w1 - k - j;
+      ++sa;
+      ++sb;
+      // parents: uniform coarse rows for even and odd lanes
+      const int pj = j & 1, pk = k & 1;
+      const int q0 = (pj << 1) | (pk << 2), q1 = q0 | 1;
+      int di0, dj0, dk0, di1, dj1, dk1;
+      parity_dir(q0, di0, dj0, dk0);
+      parity_dir(q1, di1, dj1, dk1);
+      const int di = odd ? di1 : di0;
+      auto parent = [&](int sgn, unsigned& off, bool& zero) {
+        const int jr0 = (j + sgn * dj0) >> 1, kr0 = (k + sgn * dk0) >> 1;
+        const int jr1 = (j + sgn * dj1) >> 1, kr1 = (k + sgn * dk1) >> 1;
+        const CRow R0 = crow(Lc, jr0, kr0), R1 = crow(Lc, jr1, kr1);
+        const int mbc = odd ? R1.mb : R0.mb, sac = odd ? R1.sa : R0.sa;
+        const int sbc = odd ? R1.sb : R0.sb, ec = odd ? R1.e : R0.e;
+        const int jr = odd ? jr1 : jr0, kr = odd ? kr1 : kr0;
+        const int ic = (i + sgn * di) >> 1;
+        int e2 = (ic == ec) ? sbc : mbc + ic;
+        e2 = (ic == 0) ? sac : e2;
+        const int cls = (ic == 0) | ((jr == 0) << 1) | ((kr == 0) << 2) | ((ic == ec) << 3);
+        off = valid ? (unsigned)e2 * (unsigned)sizeof(T) : HT_OOB;
+        zero = ((dmask >> cls) & 1u) != 0;
+      };
+      parent(-1, oa[r], za[r]);
+      parent(+1, ob[r], zb[r]);
     }
-    uf[slot_of(Lf, i, j, k)] += v;
+    T u[kWalkRows], va[kWalkRows], vb[kWalkRows];
+#pragma unroll
+    for (int r = 0; r < kWalkRows; ++r) {
+      bload(u[r], ru, ou[r]);
+      bload(va[r], rc, oa[r]);
+      bload(vb[r], rc, ob[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kWalkRows; ++r) {
+      const T x = za[r] ? (T)0 : va[r];
+      const T y = zb[r] ? (T)0 : vb[r];
+      bstore(u[r] + (T)0.5 * (x + y), ru, ou[r]);
+    }
   }
 }
 
-// Elementwise kernels over closure rows.
+// Elementwise kernels over the closure points.  Per plane, the offsets of
+// all rows of the tile are formed first and every load is issued before any
+// result is used.
 template <typename T, int EOP>
 __global__ __launch_bounds__(64) void k_elem(ElemArgs a) {
+  int64_t cell, w;
+  int i0, j0;
+  if (!walk_block(a.nblocks, a.ntiles, a.tiles, cell, i0, j0, w)) return;
+  __shared__ ClassInfo ci[16];
+  if (threadIdx.x < 16) ci[threadIdx.x] = a.cls[cell * 16 + threadIdx.x];
+  __syncthreads();
   const Lay L{a.n, a.stride, a.off_s0, a.off_s1};
-  int j, k;
-  if (!decode_row(L.n, blockIdx.x, j, k)) return;
-  const int64_t cell = blockIdx.y;
-  const ClassInfo* ci = a.cls + cell * 16;
-  const int e = L.n - j - k;
+  const int64_t cb = cell * L.stride;
+  const int64_t bytes = L.stride * (int64_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t r0 =
+      make_rsrc(a.in0 ? (const T*)a.in0 + cb : (const T*)a.out + cb, bytes);
+  const __amdgpu_buffer_rsrc_t r1 =
+      make_rsrc(a.in1 ? (const T*)a.in1 + cb : (const T*)a.out + cb, bytes);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc((T*)a.out + cb, bytes);
+  const int n = L.n, w1 = n - 1, i = i0 + (int)threadIdx.x;
+  const int kmax = n - i0 - j0;
   double acc = 0.0;
-  for (int i = threadIdx.x; i <= e; i += 64) {
-    const int cls = point_class(L.n, i, j, k);
-    const ClassInfo c = ci[cls];
-    const int64_t s = cell * L.stride + slot_of(L, i, j, k);
+  for (int k = 0; k <= kmax; ++k) {
+    unsigned off[kWalkRows];
+    int cl[kWalkRows], elr[kWalkRows];
+    int mb = (int)(n_tet(w1) - n_tet(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
+    int sa = (int)L.off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - k)) + j0;
+    int sb = (int)L.off_s1 + (int)(n_tri(n) - n_tri(n - k)) + j0;
+#pragma unroll
+    for (int r = 0; r < kWalkRows; ++r) {
+      const int j = j0 + r;
+      const int e = n - j - k;
+      const bool valid = e >= i0 && i <= e;
+      elr[r] = i == 0 ? sa : (i == e ? sb : mb + i);
+      off[r] = valid ? (unsigned)elr[r] * (unsigned)sizeof(T) : HT_OOB;
+      cl[r] = valid ? ((i == 0) | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3)) : -1;
+      mb += w1 - k - j;
+      ++sa;
+      ++sb;
+    }
     if (EOP == EOP_ZERO_GUESS) {
       // first Jacobi sweep from u = 0: u = omega D^-1 b
-      T* u = (T*)a.out;
-      const T* b = (const T*)a.in0;
-      u[s] = (c.flags & kClsDirichlet)
-                 ? (T)0
-                 : (T)(a.alpha * a.nscale * c.inv_diag_unit) * b[s];
-    } else if (EOP == EOP_MASS) {
-      ((T*)a.out)[s] = (T)(c.mass_unit * a.nscale);
-    } else if (EOP == EOP_ZERO_INTERIOR) {
-      if (!(c.flags & kClsDirichlet)) ((T*)a.out)[s] = (T)0;
-    } else if (EOP == EOP_DOT) {
-      if ((c.flags & kClsOwner) && !(c.flags & kClsDirichlet))
-        acc += (double)((const T*)a.in0)[s] * (double)((const T*)a.in1)[s];
-    } else if (EOP == EOP_FLAGS) {
-      uint8_t f = (c.flags & kClsOwner) ? HT_SLOT_OWNER : HT_SLOT_GHOST;
-      if (c.flags & kClsDirichlet) f |= HT_SLOT_DIRICHLET;
-      ((uint8_t*)a.out)[s] = f;
-    } else if (EOP == EOP_COORDS) {
-      const double* X = a.cell_xyz + cell * 12;     // sorted by global id
-      const int8_t* ord = a.cell_order + cell * 4;  // local index per sorted
-      const int wl[4] = {L.n - i - j - k, i, j, k};
-      double p[3] = {0.0, 0.0, 0.0};
-      for (int a3 = 0; a3 < 3; ++a3) {
-        double sum = 0.0;
-        for (int q = 0; q < 4; ++q) {
-          const int wq = wl[ord[q]];
-          if (wq > 0) sum += (double)wq * X[3 * q + a3];
-        }
-        p[a3] = sum * a.alpha;
+      T bv[kWalkRows];
+#pragma unroll
+      for (int r = 0; r < kWalkRows; ++r) bload(bv[r], r0, off[r]);
+#pragma unroll
+      for (int r = 0; r < kWalkRows; ++r) {
+        const ClassInfo& c = ci[cl[r] < 0 ? 0 : cl[r]];
+        const T f = (c.flags & kClsDirichlet) ? (T)0 : (T)(a.alpha * a.nscale * c.inv_diag_unit);
+        bstore(f * bv[r], ro, off[r]);
       }
-      T* o = (T*)a.out;
-      o[3 * s] = (T)p[0];
-      o[3 * s + 1] = (T)p[1];
-      o[3 * s + 2] = (T)p[2];
+    } else if (EOP == EOP_DOT) {
+      T xv[kWalkRows], yv[kWalkRows];
+#pragma unroll
+      for (int r = 0; r < kWalkRows; ++r) {
+        bload(xv[r], r0, off[r]);
+        bload(yv[r], r1, off[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < kWalkRows; ++r) {
+        const uint8_t f = cl[r] < 0 ? 0 : ci[cl[r]].flags;
+        const bool use = (f & kClsOwner) && !(f & kClsDirichlet);
+        acc += use ? (double)xv[r] * (double)yv[r] : 0.0;
+      }
+    } else if (EOP == EOP_MASS) {
+#pragma unroll
+      for (int r = 0; r < kWalkRows; ++r)
+        bstore((T)(ci[cl[r] < 0 ? 0 : cl[r]].mass_unit * a.nscale), ro, off[r]);
+    } else if (EOP == EOP_ZERO_INTERIOR) {
+#pragma unroll
+      for (int r = 0; r < kWalkRows; ++r) {
+        const bool dir = cl[r] >= 0 && (ci[cl[r]].flags & kClsDirichlet);
+        bstore((T)0, ro, dir ? HT_OOB : off[r]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < kWalkRows; ++r) {
+        if (cl[r] < 0) continue;
+        const ClassInfo& c = ci[cl[r]];
+        const int64_t s = cb + elr[r];
+        if (EOP == EOP_FLAGS) {
+          uint8_t f = (c.flags & kClsOwner) ? HT_SLOT_OWNER : HT_SLOT_GHOST;
+          if (c.flags & kClsDirichlet) f |= HT_SLOT_DIRICHLET;
+          ((uint8_t*)a.out)[s] = f;
+        } else if (EOP == EOP_COORDS) {
+          const double* X = a.cell_xyz + cell * 12;     // sorted by global id
+          const int8_t* ord = a.cell_order + cell * 4;  // local index per sorted
+          const int j = j0 + r;
+          const int wl[4] = {n - i - j - k, i, j, k};
+          T* o = (T*)a.out;
+          for (int a3 = 0; a3 < 3; ++a3) {
+            double sum = 0.0;
+            for (int q = 0; q < 4; ++q) {
+              const int wq = wl[ord[q]];
+              if (wq > 0) sum += (double)wq * X[3 * q + a3];
+            }
+            o[3 * s + a3] = (T)(sum * a.alpha);
+          }
+        }
+      }
     }
   }
   if (EOP == EOP_DOT) {
     acc = wave_sum(acc);
-    if (threadIdx.x == 0) a.partials[cell * gridDim.x + blockIdx.x] = acc;
+    if (threadIdx.x == 0) a.partials[w] = acc;
   }
 }
 
@@ -534,14 +749,23 @@ __global__ __launch_bounds__(256) void k_flat(FlatArgs a) {
   else if (FOP == FOP_ZERO) o[s] = (TO)0;
 }
 
-// Deterministic final reduction of per-block partial sums.
-__global__ __launch_bounds__(256) void k_sum_partials(const double* p,
-                                                      int64_t count,
-                                                      double* out, int sqrt_) {
+// Deterministic two-level reduction of per-block partial sums: stage 1
+// writes 256 strided sums to p + count, stage 2 adds them in order.
+__global__ __launch_bounds__(256) void k_sum_stage1(const double* p,
+                                                    int64_t count, double* q) {
   __shared__ double red[4];
   double s = 0.0;
-  for (int64_t t = threadIdx.x; t < count; t += 256) s += p[t];
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < count; t += 256 * 256)
+    s += p[t];
   s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) q[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+__global__ __launch_bounds__(256) void k_sum_stage2(const double* q,
+                                                    double* out, int sqrt_) {
+  __shared__ double red[4];
+  double s = wave_sum(q[threadIdx.x]);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -577,10 +801,10 @@ template <typename T, int OP>
 static void launch_cell_t(const CellArgs& a, int J, hipStream_t s) {
   const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8));
   switch (J) {
-    case 4: hipLaunchKernelGGL((k_cell<T, OP, 4>), grid, dim3(64), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_cell<T, OP, 8>), grid, dim3(64), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_cell<T, OP, 16>), grid, dim3(64), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_cell<T, OP, 8>), grid, dim3(64), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_cell<T, OP, 4>), grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_cell<T, OP, 8>), grid, dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_cell<T, OP, 16>), grid, dim3(256), 0, s, a); break;
+    default: throw Error{HT_ERR_ARG, "tile rows must be 4, 8 or 16"};
   }
 }
 
@@ -588,11 +812,13 @@ void launch_cell(int dtype, int op, int J, const CellArgs& a, hipStream_t s) {
   if (dtype == HT_F64) {
     if (op == OP_APPLY) launch_cell_t<double, OP_APPLY>(a, J, s);
     else if (op == OP_RESID) launch_cell_t<double, OP_RESID>(a, J, s);
-    else launch_cell_t<double, OP_JACOBI>(a, J, s);
+    else if (op == OP_JACOBI) launch_cell_t<double, OP_JACOBI>(a, J, s);
+    else launch_cell_t<double, OP_RESTRICT>(a, J, s);
   } else {
     if (op == OP_APPLY) launch_cell_t<float, OP_APPLY>(a, J, s);
     else if (op == OP_RESID) launch_cell_t<float, OP_RESID>(a, J, s);
-    else launch_cell_t<float, OP_JACOBI>(a, J, s);
+    else if (op == OP_JACOBI) launch_cell_t<float, OP_JACOBI>(a, J, s);
+    else launch_cell_t<float, OP_RESTRICT>(a, J, s);
   }
 }
 
@@ -605,29 +831,33 @@ static void launch_exchange_t(int op, const ExchArgs& a, hipStream_t s) {
     case OP_JACOBI: hipLaunchKernelGGL((k_exchange<T, OP_JACOBI>), grid, dim3(256), 0, s, a); break;
     case OP_SYNC: hipLaunchKernelGGL((k_exchange<T, OP_SYNC>), grid, dim3(256), 0, s, a); break;
     case OP_FILL: hipLaunchKernelGGL((k_exchange<T, OP_FILL>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_exchange<T, OP_APPLY>), grid, dim3(256), 0, s, a); break;
+    case OP_RESTRICT: hipLaunchKernelGGL((k_exchange<T, OP_RESTRICT>), grid, dim3(256), 0, s, a); break;
   }
 }
 void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
   if (a.total <= 0) return;
+  if (op != OP_APPLY && op != OP_RESID && op != OP_JACOBI && op != OP_SYNC &&
+      op != OP_FILL && op != OP_RESTRICT)
+    throw Error{HT_ERR_ARG, "unknown exchange operation"};
+  // the stencil epilogues read the operand and the stencil table for the
+  // in-face corrections, Jacobi/residual also u and b
+  if ((op == OP_APPLY || op == OP_RESID || op == OP_JACOBI) && (!a.x || !a.w))
+    throw Error{HT_ERR_ARG, "exchange after a stencil pass needs x and w"};
+  if ((op == OP_RESID || op == OP_JACOBI) && (!a.u || !a.b))
+    throw Error{HT_ERR_ARG, "exchange for residual/Jacobi needs u and b"};
   if (dtype == HT_F64) launch_exchange_t<double>(op, a, s);
   else launch_exchange_t<float>(op, a, s);
 }
 
-void launch_restrict(int dtype, const XferArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)n_tri(a.nc_ + 1), (unsigned)a.ncells);
-  if (dtype == HT_F64) hipLaunchKernelGGL(k_restrict<double>, grid, dim3(64), 0, s, a);
-  else hipLaunchKernelGGL(k_restrict<float>, grid, dim3(64), 0, s, a);
-}
 void launch_prolong(int dtype, const XferArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)n_tri(a.nf + 1), (unsigned)a.ncells);
+  const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8));
   if (dtype == HT_F64) hipLaunchKernelGGL(k_prolong<double>, grid, dim3(64), 0, s, a);
   else hipLaunchKernelGGL(k_prolong<float>, grid, dim3(64), 0, s, a);
 }
 
 template <typename T>
 static void launch_elem_t(int eop, const ElemArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)n_tri(a.n + 1), (unsigned)a.ncells);
+  const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8));
   switch (eop) {
     case EOP_ZERO_GUESS: hipLaunchKernelGGL((k_elem<T, EOP_ZERO_GUESS>), grid, dim3(64), 0, s, a); break;
     case EOP_MASS: hipLaunchKernelGGL((k_elem<T, EOP_MASS>), grid, dim3(64), 0, s, a); break;
@@ -660,7 +890,10 @@ void launch_flat(int dto, int dti, int fop, const FlatArgs& a, hipStream_t s) {
 
 void launch_sum_partials(const double* p, int64_t count, double* out, bool sq,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, p, count, out,
+  // p must have room for 256 more doubles after count
+  hipLaunchKernelGGL(k_sum_stage1, dim3(256), dim3(256), 0, s, p, count,
+                     const_cast<double*>(p) + count);
+  hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(256), 0, s, p + count, out,
                      sq ? 1 : 0);
 }
 

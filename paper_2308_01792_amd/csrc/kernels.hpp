@@ -26,10 +26,14 @@ struct CellArgs {
   int64_t stride, off_s0, off_s1;
   int n;
   double omega, nscale; // nscale = 2^l (inverse diagonal scale)
+  // restriction output (coarse level layout)
+  int64_t stride_out, off_s0_out, off_s1_out;
 };
 
 struct ExchArgs {
   void* y;
+  const void* x;        // operand of the stencil pass (face corrections)
+  const void* w;        // level-scaled class stencils [nc][16][15]
   const void* u;
   const void* b;
   const DevPrim* prim;
@@ -46,6 +50,8 @@ struct XferArgs {
   const void* src;
   void* dst;
   const ClassInfo* cls;
+  const int2* tiles;    // walk tiles (64 x 8) of the walked level
+  int64_t ntiles, nblocks;
   int64_t ncells;
   int nf, nc_;          // fine and coarse n
   int64_t stride_f, off_s0_f, off_s1_f;
@@ -57,6 +63,8 @@ struct ElemArgs {
   const void* in0;
   const void* in1;
   const ClassInfo* cls;
+  const int2* tiles;    // walk tiles (64 x 8)
+  int64_t ntiles, nblocks;
   double* partials;
   const double* cell_xyz;
   const int8_t* cell_order;
@@ -85,7 +93,6 @@ struct CoarseArgs {
 
 void launch_cell(int dtype, int op, int J, const CellArgs& a, hipStream_t s);
 void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s);
-void launch_restrict(int dtype, const XferArgs& a, hipStream_t s);
 void launch_prolong(int dtype, const XferArgs& a, hipStream_t s);
 void launch_elem(int dtype, int eop, const ElemArgs& a, hipStream_t s);
 void launch_flat(int dto, int dti, int fop, const FlatArgs& a, hipStream_t s);
