@@ -156,7 +156,9 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
   const int64_t cell = wb / a.ntiles;
   const int2 tile = a.tiles[wb % a.ntiles];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // wave index, uniform over the wave: say so, so that the row bookkeeping
+  // derived from it lives in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t w = wb * 4 + wave;  // partial-sum slot of this wave
   const int i0 = tile.x, j0 = tile.y + wave * J;
   const int n = a.n;
