@@ -47,6 +47,25 @@ def parse():
     return p.parse_args()
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cell_apply_box288_l8_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2308_01792_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("sources_sha256") != h.hexdigest() or rec.get("kernel") != kernel:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(level: int, budget_s: float):
     """The oracle's assembled CSR apply (SciPy, one thread) on the same mesh at
     a level the host can assemble; GDoF/s over interior DoFs."""
@@ -165,6 +184,8 @@ def main():
     ms32 = e0.elapsed_time(e1) / args.steps
     del x32, y32
 
+    kname = f"k_cell<double, 0, {rows64}>"
+    traffic = measured_traffic(kname)
     out = {
         "metric": "GDoF/s of matrix-free P1 apply + %HBM roofline; V-cycle "
                   "time to 1e-10 FP32/FP64",
@@ -186,8 +207,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "kernel": f"k_cell<double, apply, {rows64}>",
+                     "traffic": traffic,
+                     "kernel": kname,
                      "bytes_per_launch": BYTES_PER_DOF_F64 * ndof},
         "apply_hbm_frac": round(gdofs * BYTES_PER_DOF_F64 / HBM_PEAK_GBS, 4),
         "stream_copy": {"ms": round(copy_ms, 4), "gbs": round(copy_gbs, 1),
