@@ -203,6 +203,42 @@ int ht_vcycle(ht_mesh* mesh, int level, int dtype, const ht_cycle_opts* opts,
 int ht_solve(ht_mesh* mesh, int level, const ht_solve_opts* opts, void* u,
              const void* b, ht_solve_stats* stats, ht_stream stream);
 
+/* -------------------------------------------------------------- batch -- */
+/* Many independent small problems solved together.  The paper's data
+ * structures make every problem a set of macro-cells refined in the same way
+ * (Sections 2-3), so the problems of a batch are laid side by side as one
+ * disjoint mesh and each kernel launch covers every problem that is active
+ * on a level: a V-cycle over absolute levels where problem p joins at its
+ * own finest level.  One launch sequence (captured as one hipGraph) then
+ * serves the whole batch instead of one per problem.
+ *
+ * ht_batch_create: n meshes and the finest level of each (within that
+ * mesh's level range).  The meshes' host descriptions are copied; the
+ * meshes themselves are not referenced afterwards and may be destroyed.
+ * HT_ERR_ARG for n < 1 or a NULL mesh, HT_ERR_LEVEL for a level outside a
+ * mesh's range. */
+int ht_batch_create(ht_mesh* const* meshes, const int* levels, int n,
+                    ht_batch** out);
+int ht_batch_destroy(ht_batch* batch);
+/* Number of problems, their total unknowns (interior DoFs at each problem's
+ * finest level) and total macro-cells; any output may be NULL. */
+int ht_batch_query(const ht_batch* batch, int* n_problems, int64_t* n_dofs,
+                   int64_t* n_cells);
+/* Solve A_p u_p = b_p for every problem p.  u[p], b[p]: HT_F64 device
+ * vectors in the layout of mesh p at its finest level (n_slots of
+ * ht_mesh_query for that mesh and level); u[p] holds the initial iterate
+ * and receives the solution.  Every problem runs V(nu1, nu2) cycles until
+ * its own relative residual is <= rel_tol; its result is the iterate of
+ * the cycle at which it converged (later cycles of the batch do not change
+ * it), so it equals what ht_solve computes for that problem alone, up to
+ * rounding.  stats: array of n, one per problem.  opts->precision must be
+ * HT_PREC_F64 and opts->cyc.coarse_level must not exceed any problem's
+ * finest level.  Synchronises once per cycle.  HT_ERR_NOT_CONVERGED if
+ * some problem did not converge (all stats filled, all u[p] written). */
+int ht_batch_solve(ht_batch* batch, const ht_solve_opts* opts,
+                   void* const* u, const void* const* b, ht_solve_stats* stats,
+                   ht_stream stream);
+
 /* ------------------------------------------------------------- tuning -- */
 /* The stencil kernel runs one wavefront per tile of 64 i-points x R rows,
  * marching in k.  R in {4, 8, 16} trades register pressure against halo

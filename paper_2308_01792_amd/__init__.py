@@ -16,7 +16,7 @@ from ._lib import (HT_F32, HT_F64, HT_PREC_F64, HT_PREC_MIXED,
                    HT_SLOT_DIRICHLET, HT_SLOT_GHOST, HT_SLOT_OWNER,
                    HT_SLOT_PAD, HytetError, check)
 
-__all__ = ["Mesh", "HytetError", "load", "HT_F64", "HT_F32", "HT_PREC_F64",
+__all__ = ["Mesh", "Batch", "HytetError", "load", "HT_F64", "HT_F32", "HT_PREC_F64",
            "HT_PREC_MIXED", "HT_SLOT_OWNER", "HT_SLOT_GHOST",
            "HT_SLOT_DIRICHLET", "HT_SLOT_PAD", "index_tw",
            "selftest_lane_shift"]
@@ -254,3 +254,59 @@ class Mesh:
         check(load().ht_profile_query(self._h, prefix.encode(), C.byref(ms),
                                       C.byref(n)))
         return ms.value, n.value
+
+
+def _stats_dict(st):
+    return {"cycles": st.cycles, "converged": bool(st.converged),
+            "rel_res": st.rel_res, "seconds": st.seconds,
+            "history": list(st.res_history[:st.cycles + 1])}
+
+
+class Batch:
+    """Independent problems (mesh, finest level) solved together."""
+
+    def __init__(self, meshes, levels):
+        lib = load()
+        n = len(meshes)
+        arr = (C.c_void_p * n)(*[m._h.value for m in meshes])
+        lv = (C.c_int * n)(*[int(x) for x in levels])
+        h = C.c_void_p()
+        check(lib.ht_batch_create(arr, lv, n, C.byref(h)))
+        self._h = h
+        self.levels = list(levels)
+        self.n = n
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ht_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        n, d, c = C.c_int(), C.c_int64(), C.c_int64()
+        check(load().ht_batch_query(self._h, C.byref(n), C.byref(d),
+                                    C.byref(c)))
+        return {"problems": n.value, "dofs": d.value, "cells": c.value}
+
+    def solve(self, us, bs, rel_tol=1e-10, max_cycles=100, nu1=2, nu2=2,
+              omega=2.0 / 3.0, coarse_level=2, use_graph=True,
+              raise_on_fail=True):
+        """Solve every problem; us[p], bs[p] are float64 device vectors of
+        problem p's mesh at its finest level.  Returns per-problem stats."""
+        if len(us) != self.n or len(bs) != self.n:
+            raise ValueError("need one u and one b per problem")
+        up = (C.c_void_p * self.n)(*[_ptr(u).value for u in us])
+        bp = (C.c_void_p * self.n)(*[_ptr(b).value for b in bs])
+        o = _lib.SolveOpts(Mesh.cycle_opts(nu1, nu2, omega, coarse_level),
+                           HT_PREC_F64, rel_tol, max_cycles, int(use_graph))
+        st = (_lib.SolveStats * self.n)()
+        code = load().ht_batch_solve(self._h, C.byref(o), up, bp, st,
+                                     _stream())
+        if code != _lib.HT_ERR_NOT_CONVERGED or raise_on_fail:
+            check(code)
+        return [_stats_dict(x) for x in st]

@@ -74,6 +74,11 @@ SIGNATURES = {
     "ht_vcycle": (I, [P, I, I, C.POINTER(CycleOpts), P, P, P]),
     "ht_solve": (I, [P, I, C.POINTER(SolveOpts), P, P,
                      C.POINTER(SolveStats), P]),
+    "ht_batch_create": (I, [C.POINTER(P), C.POINTER(I), I, C.POINTER(P)]),
+    "ht_batch_destroy": (I, [P]),
+    "ht_batch_query": (I, [P, C.POINTER(I), C.POINTER(L), C.POINTER(L)]),
+    "ht_batch_solve": (I, [P, C.POINTER(SolveOpts), C.POINTER(P),
+                           C.POINTER(P), C.POINTER(SolveStats), P]),
     "ht_set_tile_rows": (I, [P, I, I, I]),
     "ht_get_tile_rows": (I, [P, I, I, C.POINTER(I)]),
     "ht_autotune": (I, [P, I, I, C.c_char_p, C.POINTER(I), P]),

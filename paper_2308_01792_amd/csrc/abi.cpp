@@ -13,6 +13,28 @@
 #include "hytet_impl.hpp"
 #include "kernels.hpp"
 
+struct ht_mesh;
+namespace ht {
+// A batch: the problems' meshes laid side by side as one disjoint mesh
+// (problems sorted by finest level, descending) plus the bookkeeping of the
+// per-problem norms.
+struct Batch {
+  int nprob = 0;
+  std::vector<int> order;         // merged problem -> caller index
+  std::vector<int> level;         // finest level per merged problem
+  std::vector<int64_t> ndofs;     // unknowns per merged problem
+  int lmax = 0, lmin = 0;         // range of finest levels
+  std::vector<int> pd0, pd1;      // per level: problems whose finest level it is
+  std::vector<int64_t> part_off;  // per level: start of its norm partials
+  int64_t part_size = 0;
+  double* d_part = nullptr;
+  int64_t* d_lo = nullptr;        // per merged problem: partial range
+  int64_t* d_hi = nullptr;
+  double* d_norm2 = nullptr;      // per merged problem
+  double* h_norm2 = nullptr;      // pinned copy
+};
+}  // namespace ht
+
 struct ht_mesh {
   ht::Mesh m;
   // (level, J) -> tile list on the device
@@ -66,9 +88,15 @@ static void check_ptr(const void* p, const char* what) {
     throw Error{HT_ERR_ARG, std::string(what) + " is not 256-byte aligned"};
 }
 static size_t esize(int dtype) { return dtype == HT_F64 ? 8 : 4; }
+// Address of the first slot of cell c0 in a level vector.
+template <typename P>
+static P* at_cell(P* v, int64_t c0, int level, int dtype) {
+  return v ? (P*)((const char*)v + c0 * make_layout(level).stride * (int64_t)esize(dtype)) : v;
+}
 
+// Slots of a level vector: the cells of the problems present on the level.
 int64_t level_slots(const Mesh& m, int level) {
-  return m.nc * make_layout(level).stride;
+  return m.act_cells[level] * make_layout(level).stride;
 }
 
 template <typename T>
@@ -225,19 +253,27 @@ static int choose_J(ht_mesh* h, int level, int dtype) {
   return 8;
 }
 
+// Stencil-kernel arguments over the cells of R: every per-cell array is
+// addressed from the range's first cell.
+static const void* level_weights(ht_mesh* h, int level, int dtype) {
+  return dtype == HT_F64 ? (const void*)h->m.d_w64[level] : (const void*)h->m.d_w32[level];
+}
 static CellArgs cell_args(ht_mesh* h, int level, int dtype, int J,
-                          const void* x, void* y, const void* b, double omega) {
+                          const void* x, void* y, const void* b, double omega,
+                          const Range& R) {
   Mesh& m = h->m;
   const CellLayout L = make_layout(level);
   CellArgs a{};
-  a.x = x; a.y = y; a.b = b;
-  a.w = dtype == HT_F64 ? (const void*)m.d_w64[level] : (const void*)m.d_w32[level];
-  a.cls = m.d_cls;
+  a.x = at_cell(x, R.c0, level, dtype);
+  a.y = at_cell(y, R.c0, level, dtype);
+  a.b = at_cell(b, R.c0, level, dtype);
+  a.w = (const char*)level_weights(h, level, dtype) + R.c0 * 240 * (int64_t)esize(dtype);
+  a.cls = m.d_cls + 16 * R.c0;
   a.partials = m.d_partials;
   auto& t = h->tiles.at({level, J});
   a.tiles = t.first;
   a.ntiles = t.second;
-  a.nblocks = m.nc * t.second;
+  a.nblocks = (R.c1 - R.c0) * t.second;
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
   a.n = L.n;
   a.omega = omega;
@@ -245,8 +281,11 @@ static CellArgs cell_args(ht_mesh* h, int level, int dtype, int J,
   return a;
 }
 
+// Exchange arguments over the shared primitives of R; vectors and weights
+// stay absolute (incidences name absolute cells).
 static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
-                          const void* b, double omega, double* partials) {
+                          const void* b, double omega, double* partials,
+                          const Range& R) {
   Mesh& m = h->m;
   const CellLayout L = make_layout(level);
   const int n = L.n;
@@ -256,11 +295,14 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
   a.partials = partials;
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
   a.n = n;
-  a.n_faces = m.n_faces; a.n_edges = m.n_edges;
+  a.n_faces = R.f1 - R.f0; a.n_edges = R.e1 - R.e0;
+  a.prim_f0 = R.f0;
+  a.prim_e0 = m.n_faces + R.e0;
+  a.prim_v0 = m.n_faces + m.n_edges + R.v0;
   a.face_pts = n_tri(n - 2);
-  a.face_end = m.n_faces * a.face_pts;
-  a.edge_end = a.face_end + m.n_edges * std::max(n - 1, 0);
-  a.total = a.edge_end + m.n_verts;
+  a.face_end = a.n_faces * a.face_pts;
+  a.edge_end = a.face_end + a.n_edges * std::max(n - 1, 0);
+  a.total = a.edge_end + (R.v1 - R.v0);
   a.omega = omega;
   a.nscale = (double)n;
   return a;
@@ -270,21 +312,22 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
 // of the result lands in m.d_scalar[slot] (device) when want_norm.
 static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
                     void* y, const void* b, double omega, hipStream_t s,
-                    bool want_norm = false, int scalar_slot = 0) {
+                    bool want_norm, int scalar_slot, const Range& R) {
   Mesh& m = h->m;
+  if (R.empty()) return;
   const int J = choose_J(h, level, dtype);
-  CellArgs ca = cell_args(h, level, dtype, J, x, y, b, omega);
+  CellArgs ca = cell_args(h, level, dtype, J, x, y, b, omega, R);
   {
     Prof p(h, op == OP_APPLY ? "cell_apply" : op == OP_RESID ? "cell_residual" : "cell_jacobi", s);
     launch_cell(dtype, op, J, ca, s);
     check_launch();
   }
   ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
-                          m.d_partials + 4 * ca.nblocks);
+                          m.d_partials + 4 * ca.nblocks, R);
   if (op == OP_RESID) ea.u = x;
   ea.x = x;
-  ea.w = ca.w;
-  {
+  ea.w = level_weights(h, level, dtype);
+  if (ea.total > 0) {
     Prof p(h, "exchange", s);
     launch_exchange(dtype, op, ea, s);
     check_launch();
@@ -297,57 +340,89 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
   }
 }
 
+static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
+                    void* y, const void* b, double omega, hipStream_t s,
+                    bool want_norm = false, int scalar_slot = 0) {
+  op_pass(h, level, dtype, op, x, y, b, omega, s, want_norm, scalar_slot,
+          full_range(h->m));
+}
+
 static void exch_only(ht_mesh* h, int level, int dtype, int op, void* v,
                       double fill, hipStream_t s) {
-  ExchArgs ea = exch_args(h, level, v, nullptr, nullptr, 0.0, h->m.d_partials);
+  ExchArgs ea = exch_args(h, level, v, nullptr, nullptr, 0.0, h->m.d_partials,
+                          full_range(h->m));
+  if (ea.total == 0) return;
   ea.fill = fill;
   Prof p(h, op == OP_SYNC ? "sync" : "fill", s);
   launch_exchange(dtype, op, ea, s);
   check_launch();
 }
 
-static ElemArgs elem_args(ht_mesh* h, int level) {
+// Elementwise-kernel arguments over the cells of R (vectors must be given
+// at_cell(v, R.c0, ...) by the caller).
+static ElemArgs elem_args(ht_mesh* h, int level, const Range& R) {
   Mesh& m = h->m;
   const CellLayout L = make_layout(level);
   ElemArgs a{};
-  a.cls = m.d_cls;
+  a.cls = m.d_cls + 16 * R.c0;
   a.partials = m.d_partials;
-  a.cell_xyz = m.d_cell_xyz;
-  a.cell_order = m.d_cell_order;
-  a.ncells = m.nc;
+  a.cell_xyz = m.d_cell_xyz + 12 * R.c0;
+  a.cell_order = m.d_cell_order + 4 * R.c0;
+  a.ncells = R.c1 - R.c0;
   a.n = L.n;
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
   a.nscale = (double)L.n;
   auto& t = h->walk_tiles.at(level);
   a.tiles = t.first;
   a.ntiles = t.second;
-  a.nblocks = m.nc * t.second;
+  a.nblocks = a.ncells * t.second;
   return a;
+}
+static ElemArgs elem_args(ht_mesh* h, int level) {
+  return elem_args(h, level, full_range(h->m));
 }
 
 static void flat(ht_mesh* h, int level, int dto, int dti, int fop, void* out,
                  const void* in, hipStream_t s) {
   FlatArgs a{out, in, level_slots(h->m, level)};
+  if (a.count == 0) return;
+  Prof p(h, "flat", s);
+  launch_flat(dto, dti, fop, a, s);
+  check_launch();
+}
+
+// flat over the cells of R only
+static void flat_range(ht_mesh* h, int level, int dto, int dti, int fop,
+                       void* out, const void* in, hipStream_t s, const Range& R) {
+  FlatArgs a{at_cell(out, R.c0, level, dto), at_cell(in, R.c0, level, dti),
+             (R.c1 - R.c0) * make_layout(level).stride};
+  if (a.count == 0) return;
   Prof p(h, "flat", s);
   launch_flat(dto, dti, fop, a, s);
   check_launch();
 }
 
 static void zero_guess_sweep(ht_mesh* h, int level, int dtype, double omega,
-                             void* u, const void* b, hipStream_t s) {
-  ElemArgs a = elem_args(h, level);
-  a.out = u; a.in0 = b; a.alpha = omega;
+                             void* u, const void* b, hipStream_t s,
+                             const Range& R) {
+  if (R.empty()) return;
+  ElemArgs a = elem_args(h, level, R);
+  a.out = at_cell(u, R.c0, level, dtype);
+  a.in0 = at_cell(b, R.c0, level, dtype);
+  a.alpha = omega;
   Prof p(h, "zero_guess", s);
   launch_elem(dtype, EOP_ZERO_GUESS, a, s);
   check_launch();
 }
 
 static void restrict_pass(ht_mesh* h, int fine, int dtype, const void* rf,
-                          void* rc, hipStream_t s) {
+                          void* rc, hipStream_t s, const Range& R) {
   Mesh& m = h->m;
+  if (R.empty()) return;
   const CellLayout Lc = make_layout(fine - 1);
   const int J = choose_J(h, fine, dtype);
-  CellArgs ca = cell_args(h, fine, dtype, J, rf, rc, nullptr, 0.0);
+  CellArgs ca = cell_args(h, fine, dtype, J, rf, nullptr, nullptr, 0.0, R);
+  ca.y = at_cell(rc, R.c0, fine - 1, dtype);
   ca.stride_out = Lc.stride;
   ca.off_s0_out = Lc.off_s0;
   ca.off_s1_out = Lc.off_s1;
@@ -356,24 +431,29 @@ static void restrict_pass(ht_mesh* h, int fine, int dtype, const void* rf,
     launch_cell(dtype, OP_RESTRICT, J, ca, s);
     check_launch();
   }
-  ExchArgs ea = exch_args(h, fine - 1, rc, nullptr, nullptr, 0.0, m.d_partials);
+  ExchArgs ea = exch_args(h, fine - 1, rc, nullptr, nullptr, 0.0, m.d_partials, R);
+  if (ea.total == 0) return;
   Prof p(h, "exchange", s);
   launch_exchange(dtype, OP_RESTRICT, ea, s);
   check_launch();
 }
 
 static void prolong_pass(ht_mesh* h, int coarse, int dtype, const void* ec,
-                         void* uf, hipStream_t s) {
+                         void* uf, hipStream_t s, const Range& R) {
   Mesh& m = h->m;
+  if (R.empty()) return;
   const CellLayout Lf = make_layout(coarse + 1), Lc = make_layout(coarse);
   XferArgs a{};
-  a.src = ec; a.dst = uf; a.cls = m.d_cls; a.ncells = m.nc;
+  a.src = at_cell(ec, R.c0, coarse, dtype);
+  a.dst = at_cell(uf, R.c0, coarse + 1, dtype);
+  a.cls = m.d_cls + 16 * R.c0;
+  a.ncells = R.c1 - R.c0;
   a.nf = Lf.n; a.nc_ = Lc.n;
   a.stride_f = Lf.stride; a.off_s0_f = Lf.off_s0; a.off_s1_f = Lf.off_s1;
   a.stride_c = Lc.stride; a.off_s0_c = Lc.off_s0; a.off_s1_c = Lc.off_s1;
   {
     auto& t = h->walk_tiles.at(coarse + 1);
-    a.tiles = t.first; a.ntiles = t.second; a.nblocks = m.nc * t.second;
+    a.tiles = t.first; a.ntiles = t.second; a.nblocks = a.ncells * t.second;
   }
   Prof p(h, "prolongate", s);
   launch_prolong(dtype, a, s);
@@ -390,6 +470,9 @@ static CoarseSolver& coarse_solver(ht_mesh* h, int level) {
   cs.d_owner = upload(cs.owner_slot);
   cs.d_copy_ptr = upload(cs.copy_ptr);
   cs.d_copy_slot = upload(cs.copy_slot);
+  cs.d_blk_dof = upload(cs.blk_dof);
+  cs.d_blk_inv = upload(cs.blk_inv);
+  cs.d_row_blk = upload(cs.row_blk);
   cs.d_rhs = dalloc<double>(std::max<int64_t>(cs.ndof, 1));
   return cs;
 }
@@ -398,7 +481,8 @@ static CoarseSolver& coarse_solver(ht_mesh* h, int level) {
 static void coarse_fast(ht_mesh* h, int level, int dtype, const void* b,
                         void* u, hipStream_t s) {
   CoarseSolver& cs = coarse_solver(h, level);
-  CoarseArgs a{b, u, cs.d_inv, cs.d_owner, cs.d_copy_ptr, cs.d_copy_slot, cs.d_rhs, cs.ndof};
+  CoarseArgs a{b, u, cs.d_inv, cs.d_owner, cs.d_copy_ptr, cs.d_copy_slot,
+               cs.d_blk_dof, cs.d_blk_inv, cs.d_row_blk, cs.d_rhs, cs.ndof};
   Prof p(h, "coarse_solve", s);
   launch_coarse(dtype, a, s);
   check_launch();
@@ -441,7 +525,7 @@ static void* vcycle_impl(ht_mesh* h, int level, int dtype,
   int todo = o.nu1;
   if (zero_guess) {
     if (todo > 0) {
-      zero_guess_sweep(h, level, dtype, o.omega, cur, b, s);
+      zero_guess_sweep(h, level, dtype, o.omega, cur, b, s, full_range(h->m));
       --todo;
     } else {
       flat(h, level, dtype, dtype, FOP_ZERO, cur, nullptr, s);
@@ -451,9 +535,9 @@ static void* vcycle_impl(ht_mesh* h, int level, int dtype,
   other = (cur == u) ? t : u;
   op_pass(h, level, dtype, OP_RESID, cur, other, b, 0.0, s);
   LevelWork& wc = work(h, level - 1, dtype);
-  restrict_pass(h, level, dtype, other, wc.b, s);
+  restrict_pass(h, level, dtype, other, wc.b, s, full_range(h->m));
   void* ec = vcycle_impl(h, level - 1, dtype, o, wc.u, wc.t, wc.b, true, s);
-  prolong_pass(h, level - 1, dtype, ec, cur, s);
+  prolong_pass(h, level - 1, dtype, ec, cur, s, full_range(h->m));
   return sweeps(h, level, dtype, o.omega, o.nu2, cur, other, b, s);
 }
 
@@ -525,7 +609,83 @@ static void run_graph(ht_mesh* h, const std::string& key,
   HT_CHECK_HIP(hipGraphLaunch(it->second.exec, s));
 }
 
+
+// ------------------------------------------------------------- batch ----
+// Per-problem squared norms of (which = 0) the residual b - A u or (1) b at
+// each problem's finest level, into bt.d_norm2 and its pinned copy.
+static void batch_norms(ht_mesh* h, Batch& bt, int which, hipStream_t s) {
+  Mesh& m = h->m;
+  for (int l = bt.lmax; l >= bt.lmin; --l) {
+    if (bt.pd1[l] <= bt.pd0[l]) continue;
+    const Range D = problem_range(m, bt.pd0[l], bt.pd1[l]);
+    LevelWork& w = work(h, l, HT_F64);
+    const void* v = w.b;
+    if (which == 0) {
+      op_pass(h, l, HT_F64, OP_RESID, w.u, w.t, w.b, 0.0, s, false, 0, D);
+      v = w.t;
+    }
+    ElemArgs a = elem_args(h, l, D);
+    a.in0 = a.in1 = at_cell(v, D.c0, l, HT_F64);
+    a.partials = bt.d_part + bt.part_off[l];
+    Prof p(h, "dot", s);
+    launch_elem(HT_F64, EOP_DOT, a, s);
+    check_launch();
+  }
+  SegArgs sa{bt.d_part, bt.d_lo, bt.d_hi, bt.d_norm2, bt.nprob};
+  launch_seg_sum(sa, s);
+  check_launch();
+  HT_CHECK_HIP(hipMemcpyAsync(bt.h_norm2, bt.d_norm2, bt.nprob * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+}
+
+// One V-cycle over absolute levels.  On level l the problems [0, pd1[l])
+// are active: those with a finer finest level carry a coarse correction
+// (zero initial guess, right-hand side restricted from l + 1), those whose
+// finest level is l carry their iterate.  The result is left in work(l).u.
+static void batch_level(ht_mesh* h, Batch& bt, int l, const ht_cycle_opts& o,
+                        hipStream_t s) {
+  Mesh& m = h->m;
+  LevelWork& w = work(h, l, HT_F64);
+  if (l == o.coarse_level) {
+    coarse_fast(h, l, HT_F64, w.b, w.u, s);
+    return;
+  }
+  const Range A = problem_range(m, 0, bt.pd1[l]);
+  const Range C = problem_range(m, 0, bt.pd0[l]);
+  const Range D = problem_range(m, bt.pd0[l], bt.pd1[l]);
+  void* cur = w.u;
+  void* oth = w.t;
+  int todo = o.nu1;
+  if (todo > 0) {
+    zero_guess_sweep(h, l, HT_F64, o.omega, oth, w.b, s, C);
+    op_pass(h, l, HT_F64, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, D);
+    std::swap(cur, oth);
+    --todo;
+  } else {
+    flat_range(h, l, HT_F64, HT_F64, FOP_ZERO, cur, nullptr, s, C);
+  }
+  for (; todo > 0; --todo) {
+    op_pass(h, l, HT_F64, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, A);
+    std::swap(cur, oth);
+  }
+  op_pass(h, l, HT_F64, OP_RESID, cur, oth, w.b, 0.0, s, false, 0, A);
+  LevelWork& wc = work(h, l - 1, HT_F64);
+  restrict_pass(h, l, HT_F64, oth, wc.b, s, A);
+  batch_level(h, bt, l - 1, o, s);
+  prolong_pass(h, l - 1, HT_F64, wc.u, cur, s, A);
+  for (int k = 0; k < o.nu2; ++k) {
+    op_pass(h, l, HT_F64, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, A);
+    std::swap(cur, oth);
+  }
+  if (cur != w.u) flat_range(h, l, HT_F64, HT_F64, FOP_COPY, w.u, cur, s, A);
+}
+
 }  // namespace ht
+
+struct ht_batch {
+  ht_mesh* mesh = nullptr;  // the disjoint union of the problems
+  ht::Batch bt;
+};
 
 using namespace ht;
 
@@ -565,6 +725,8 @@ int ht_mesh_destroy(ht_mesh* h) {
       for (auto& kv : m.coarse) {
         (void)hipFree(kv.second.d_inv); (void)hipFree(kv.second.d_owner);
         (void)hipFree(kv.second.d_copy_ptr); (void)hipFree(kv.second.d_copy_slot);
+        (void)hipFree(kv.second.d_blk_dof); (void)hipFree(kv.second.d_blk_inv);
+        (void)hipFree(kv.second.d_row_blk);
         (void)hipFree(kv.second.d_rhs);
       }
       for (auto& e : m.prof) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
@@ -801,7 +963,7 @@ int ht_restrict(ht_mesh* h, int fine_level, int dtype, const void* rf, void* rc,
     check_level(h->m, fine_level - 1);
     check_ptr(rf, "r_fine");
     check_ptr(rc, "r_coarse");
-    restrict_pass(h, fine_level, dtype, rf, rc, s);
+    restrict_pass(h, fine_level, dtype, rf, rc, s, full_range(h->m));
   });
 }
 
@@ -812,7 +974,7 @@ int ht_prolongate_add(ht_mesh* h, int coarse_level, int dtype, const void* ec,
     check_level(h->m, coarse_level + 1);
     check_ptr(ec, "e_coarse");
     check_ptr(uf, "u_fine");
-    prolong_pass(h, coarse_level, dtype, ec, uf, s);
+    prolong_pass(h, coarse_level, dtype, ec, uf, s, full_range(h->m));
   });
 }
 
@@ -917,6 +1079,222 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
                                             " after " + std::to_string(k) + " cycles"};
   });
   return rc;
+}
+
+int ht_batch_create(ht_mesh* const* meshes, const int* levels, int n,
+                    ht_batch** out) {
+  return guard([&] {
+    if (!out || !meshes || !levels || n < 1)
+      throw Error{HT_ERR_ARG, "need n >= 1 meshes, levels and out"};
+    *out = nullptr;
+    for (int p = 0; p < n; ++p) {
+      if (!meshes[p]) throw Error{HT_ERR_ARG, "mesh " + std::to_string(p) + " is NULL"};
+      check_level(meshes[p]->m, levels[p]);
+    }
+    std::vector<int> order(n);
+    for (int p = 0; p < n; ++p) order[p] = p;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return levels[a] > levels[b]; });
+    std::vector<double> xyz;
+    std::vector<int64_t> cells, cell_begin{0};
+    std::vector<int> fin;
+    int lo = 10;
+    for (int q : order) {
+      const Mesh& src = meshes[q]->m;
+      const int64_t voff = (int64_t)xyz.size() / 3;
+      xyz.insert(xyz.end(), src.xyz.begin(), src.xyz.end());
+      for (const Cell& c : src.cells)
+        for (int k = 0; k < 4; ++k) cells.push_back(c.gv[k] + voff);
+      cell_begin.push_back(cell_begin.back() + src.nc);
+      fin.push_back(levels[q]);
+      lo = std::min(lo, src.min_level);
+    }
+    auto B = std::make_unique<ht_batch>();
+    B->mesh = new ht_mesh();
+    Mesh& m = B->mesh->m;
+    build_mesh(m, xyz.data(), (int64_t)xyz.size() / 3, cells.data(),
+               (int64_t)cells.size() / 4, lo, fin.front());
+    set_problems(m, cell_begin, fin);
+    Batch& bt = B->bt;
+    bt.nprob = n;
+    bt.order = order;
+    bt.level = fin;
+    bt.lmax = fin.front();
+    bt.lmin = fin.back();
+    bt.pd0.assign(bt.lmax + 2, 0);
+    bt.pd1.assign(bt.lmax + 2, 0);
+    for (int l = 0; l <= bt.lmax + 1; ++l) {
+      int a = 0, b = 0;
+      while (a < n && fin[a] > l) ++a;
+      while (b < n && fin[b] >= l) ++b;
+      bt.pd0[l] = a;
+      bt.pd1[l] = b;
+    }
+    for (int p = 0; p < n; ++p) {
+      ht_level_info li;
+      if (ht_mesh_query(meshes[order[p]], fin[p], &li) != HT_OK)
+        throw Error{HT_ERR_ARG, g_last_error};
+      bt.ndofs.push_back(li.n_dofs);
+    }
+    *out = B.release();
+  });
+}
+
+int ht_batch_destroy(ht_batch* B) {
+  return guard([&] {
+    if (!B) return;
+    Batch& bt = B->bt;
+    if (bt.d_part) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(bt.d_part); (void)hipFree(bt.d_lo); (void)hipFree(bt.d_hi);
+      (void)hipFree(bt.d_norm2); (void)hipHostFree(bt.h_norm2);
+    }
+    ht_mesh_destroy(B->mesh);
+    delete B;
+  });
+}
+
+int ht_batch_query(const ht_batch* B, int* n_problems, int64_t* n_dofs,
+                   int64_t* n_cells) {
+  return guard([&] {
+    if (!B) throw Error{HT_ERR_ARG, "batch is NULL"};
+    if (n_problems) *n_problems = B->bt.nprob;
+    if (n_dofs) {
+      int64_t t = 0;
+      for (int64_t d : B->bt.ndofs) t += d;
+      *n_dofs = t;
+    }
+    if (n_cells) *n_cells = B->mesh->m.nc;
+  });
+}
+
+int ht_batch_solve(ht_batch* B, const ht_solve_opts* o, void* const* u,
+                   const void* const* b, ht_solve_stats* st, ht_stream stream) {
+  return guard([&] {
+    if (!B || !o || !u || !b || !st) throw Error{HT_ERR_ARG, "NULL argument"};
+    ht_mesh* h = B->mesh;
+    Mesh& m = h->m;
+    Batch& bt = B->bt;
+    const int P = bt.nprob;
+    if (o->precision != HT_PREC_F64)
+      throw Error{HT_ERR_ARG, "batch solves run in FP64 (HT_PREC_F64)"};
+    if (o->max_cycles < 0 || o->max_cycles > 256)
+      throw Error{HT_ERR_ARG, "max_cycles must be in [0, 256]"};
+    check_cycle(m, bt.lmax, &o->cyc);
+    if (o->cyc.coarse_level > bt.lmin)
+      throw Error{HT_ERR_LEVEL, "coarse_level above the finest level of a problem"};
+    for (int q = 0; q < P; ++q) {
+      check_ptr(u[q], "u[p]");
+      check_ptr(b[q], "b[p]");
+    }
+    ensure_uploaded_h(h);
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    // set-up before any capture: workspace, coarse solver, norm tables
+    coarse_solver(h, o->cyc.coarse_level);
+    for (int l = o->cyc.coarse_level; l <= bt.lmax; ++l) work(h, l, HT_F64);
+    if (!bt.d_part) {
+      bt.part_off.assign(bt.lmax + 1, 0);
+      int64_t off = 0;
+      std::vector<int64_t> lo(P), hi(P);
+      for (int l = bt.lmax; l >= bt.lmin; --l) {
+        bt.part_off[l] = off;
+        if (bt.pd1[l] <= bt.pd0[l]) continue;
+        const int64_t nw = h->walk_tiles.at(l).second;
+        const int64_t cbase = m.pcell[bt.pd0[l]];
+        for (int p = bt.pd0[l]; p < bt.pd1[l]; ++p) {
+          lo[p] = off + (m.pcell[p] - cbase) * nw;
+          hi[p] = off + (m.pcell[p + 1] - cbase) * nw;
+        }
+        off += (m.pcell[bt.pd1[l]] - cbase) * nw;
+      }
+      bt.part_size = off;
+      bt.d_part = dalloc<double>(std::max<int64_t>(off, 1));
+      bt.d_lo = upload(lo);
+      bt.d_hi = upload(hi);
+      bt.d_norm2 = dalloc<double>(P);
+      HT_CHECK_HIP(hipHostMalloc((void**)&bt.h_norm2, P * sizeof(double),
+                                 hipHostMallocDefault));
+    }
+    // a problem's vector is the run of slots of its cells on its finest level
+    auto seg = [&](int p, void* v) {
+      return at_cell(v, m.pcell[p], bt.level[p], HT_F64);
+    };
+    auto seg_bytes = [&](int p) {
+      return (size_t)((m.pcell[p + 1] - m.pcell[p]) * make_layout(bt.level[p]).stride * 8);
+    };
+    for (int p = 0; p < P; ++p) {
+      LevelWork& w = work(h, bt.level[p], HT_F64);
+      HT_CHECK_HIP(hipMemcpyAsync(seg(p, w.u), u[bt.order[p]], seg_bytes(p),
+                                  hipMemcpyDeviceToDevice, s));
+      HT_CHECK_HIP(hipMemcpyAsync(seg(p, w.b), b[bt.order[p]], seg_bytes(p),
+                                  hipMemcpyDeviceToDevice, s));
+    }
+    batch_norms(h, bt, 1, s);
+    HT_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<double> scale(P);
+    for (int p = 0; p < P; ++p) {
+      const double bn = std::sqrt(bt.h_norm2[p]);
+      scale[p] = bn > 0 ? 1.0 / bn : 1.0;
+    }
+    batch_norms(h, bt, 0, s);
+    HT_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<ht_solve_stats> ps(P);
+    for (auto& x : ps) std::memset(&x, 0, sizeof(x));
+    std::vector<char> done(P, 0);
+    int open = P;
+    auto copy_out = [&](int p) {
+      LevelWork& w = work(h, bt.level[p], HT_F64);
+      HT_CHECK_HIP(hipMemcpyAsync(u[bt.order[p]], seg(p, w.u), seg_bytes(p),
+                                  hipMemcpyDeviceToDevice, s));
+    };
+    // a problem is frozen (copied out) at the first cycle that meets rel_tol
+    auto record = [&](int k) {
+      for (int p = 0; p < P; ++p) {
+        if (done[p]) continue;
+        const double rel = std::sqrt(bt.h_norm2[p]) * scale[p];
+        ps[p].res_history[k] = rel;
+        ps[p].cycles = k;
+        ps[p].rel_res = rel;
+        if (rel <= o->rel_tol || !std::isfinite(rel)) {
+          ps[p].converged = rel <= o->rel_tol;
+          done[p] = 1;
+          --open;
+          copy_out(p);
+        }
+      }
+    };
+    record(0);
+    std::ostringstream key;
+    key << "batch:" << o->cyc.nu1 << ':' << o->cyc.nu2 << ':' << o->cyc.omega
+        << ':' << o->cyc.coarse_level;
+    auto step = [&](hipStream_t ss) {
+      batch_level(h, bt, bt.lmax, o->cyc, ss);
+      batch_norms(h, bt, 0, ss);
+    };
+    int k = 0;
+    while (open > 0 && k < o->max_cycles) {
+      if (o->use_graph) run_graph(h, key.str(), step, s);
+      else step(s);
+      HT_CHECK_HIP(hipStreamSynchronize(s));
+      ++k;
+      record(k);
+    }
+    for (int p = 0; p < P; ++p)
+      if (!done[p]) copy_out(p);
+    HT_CHECK_HIP(hipStreamSynchronize(s));
+    const double sec =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int failed = 0;
+    for (int p = 0; p < P; ++p) {
+      ps[p].seconds = sec;
+      failed += !ps[p].converged;
+      st[bt.order[p]] = ps[p];
+    }
+    if (failed)
+      throw Error{HT_ERR_NOT_CONVERGED, std::to_string(failed) + " of " +
+                                            std::to_string(P) + " problems did not converge"};
+  });
 }
 
 int ht_set_tile_rows(ht_mesh* h, int level, int dtype, int rows) {

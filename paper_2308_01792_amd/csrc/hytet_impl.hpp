@@ -89,18 +89,33 @@ struct LevelWork {
   void* t = nullptr;    // Jacobi ping-pong and residual
 };
 
+// Exact coarse-level solver: A_II^-1 as dense blocks, one per independent
+// problem of the mesh (a plain mesh is one problem, one block).
 struct CoarseSolver {
   int level = -1;
   int64_t ndof = 0;
   std::vector<int64_t> owner_slot;     // slot of the owning copy per DoF
   std::vector<int64_t> copy_ptr;       // CSR over all copies of each DoF
   std::vector<int64_t> copy_slot;
-  std::vector<double> inv;             // dense inverse, row-major
+  std::vector<int64_t> blk_dof;        // DoF range of block b: [blk_dof[b], blk_dof[b+1])
+  std::vector<int64_t> blk_inv;        // start of block b's inverse in inv
+  std::vector<int32_t> row_blk;        // block of every DoF
+  std::vector<double> inv;             // dense inverse blocks, row-major
   double* d_inv = nullptr;
   int64_t* d_owner = nullptr;
   int64_t* d_copy_ptr = nullptr;
   int64_t* d_copy_slot = nullptr;
+  int64_t* d_blk_dof = nullptr;
+  int64_t* d_blk_inv = nullptr;
+  int32_t* d_row_blk = nullptr;
   double* d_rhs = nullptr;             // gathered right-hand side
+};
+
+// A contiguous run of independent problems of a mesh: its cells [c0, c1)
+// and its faces, edges and vertices (indices within each kind).
+struct Range {
+  int64_t c0, c1, f0, f1, e0, e1, v0, v1;
+  bool empty() const { return c1 <= c0; }
 };
 
 struct DevPrim {
@@ -129,6 +144,13 @@ struct Mesh {
   std::vector<Prim> prims;                // faces, then edges, then vertices
   int64_t n_faces = 0, n_edges = 0, n_verts = 0;
   std::vector<ClassInfo> cls;             // [nc][16]
+  // Independent problems (disjoint unions of meshes, see ht_batch): problem
+  // p owns cells [pcell[p], pcell[p+1]) and likewise faces, edges, vertices.
+  // act_cells[l]: cells of the problems present on level l, a prefix of the
+  // cell list (problems are sorted by finest level, descending).
+  int nprob = 1;
+  std::vector<int64_t> pcell, pface, pedge, pvert;
+  std::vector<int64_t> act_cells;         // per level
 
   // ---- device mirrors (created on first device call)
   bool uploaded = false;
@@ -165,6 +187,10 @@ void slot_key(const Mesh& m, int level, int64_t slot, int64_t key[8],
               uint8_t* flags);
 void slot_coords(const Mesh& m, int level, int64_t slot, double out[3]);
 void build_coarse_solver(Mesh& m, int level, CoarseSolver& cs);
+void set_problems(Mesh& m, const std::vector<int64_t>& cell_begin,
+                  const std::vector<int>& finest_level);
+Range problem_range(const Mesh& m, int p0, int p1);
+inline Range full_range(const Mesh& m) { return problem_range(m, 0, m.nprob); }
 void level_scaled_stencils(const Mesh& m, int level, std::vector<double>& w);
 
 // ------------------------------------------------------ device side ----

@@ -394,20 +394,21 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
     int gw[3] = {0, 0, 0};
     if (t < a.face_end) {
       const int64_t fp = a.face_pts;
-      prim = t / fp;
+      const int64_t fl = t / fp;  // face within the range
+      prim = a.prim_f0 + fl;
       int aa, bb;
-      tri_decode(t - prim * fp, n - 2, aa, bb);
+      tri_decode(t - fl * fp, n - 2, aa, bb);
       gw[1] = aa + 1;
       gw[2] = bb + 1;
       gw[0] = n - gw[1] - gw[2];
     } else if (t < a.edge_end) {
       const int64_t s = t - a.face_end;
       const int64_t ep = n - 1;
-      prim = a.n_faces + s / ep;
+      prim = a.prim_e0 + s / ep;
       gw[1] = (int)(s % ep) + 1;
       gw[0] = n - gw[1];
     } else {
-      prim = a.n_faces + a.n_edges + (t - a.edge_end);
+      prim = a.prim_v0 + (t - a.edge_end);
       gw[0] = n;
     }
     const DevPrim P = a.prim[prim];
@@ -776,21 +777,36 @@ __global__ __launch_bounds__(256) void k_sum_stage2(const double* q,
   }
 }
 
+// Segmented sums of norm partials, one wave per segment, fixed order.
+__global__ __launch_bounds__(256) void k_seg_sum(SegArgs a) {
+  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (seg >= a.nseg) return;
+  double s = 0.0;
+  for (int64_t q = a.lo[seg] + lane; q < a.hi[seg]; q += 64) s += a.p[q];
+  s = wave_sum(s);
+  if (lane == 0) a.out[seg] = s;
+}
+
 // --------------------------------------------------------- coarse solve --
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_gather(CoarseArgs a) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d < a.ndof) a.rhs[d] = (double)((const T*)a.b)[a.owner[d]];
 }
-// One wave per row of the dense inverse; the result goes to every copy.
+// One wave per row of the block-diagonal inverse; the result goes to every
+// copy.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_gemv(CoarseArgs a) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= a.ndof) return;
-  const double* r = a.inv + row * a.ndof;
+  const int b = a.row_blk[row];
+  const int64_t d0 = a.blk_dof[b], nb = a.blk_dof[b + 1] - d0;
+  const double* r = a.inv + a.blk_inv[b] + (row - d0) * nb;
+  const double* x = a.rhs + d0;
   double s = 0.0;
-  for (int64_t c = lane; c < a.ndof; c += 64) s += r[c] * a.rhs[c];
+  for (int64_t c = lane; c < nb; c += 64) s += r[c] * x[c];
   s = wave_sum(s);
   T* u = (T*)a.u;
   for (int64_t q = a.copy_ptr[row] + lane; q < a.copy_ptr[row + 1]; q += 64)
@@ -909,6 +925,11 @@ void launch_coarse(int dtype, const CoarseArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_coarse_gather<float>, g1, dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_coarse_gemv<float>, g2, dim3(256), 0, s, a);
   }
+}
+
+void launch_seg_sum(const SegArgs& a, hipStream_t s) {
+  if (a.nseg <= 0) return;
+  hipLaunchKernelGGL(k_seg_sum, dim3((unsigned)((a.nseg + 3) / 4)), dim3(256), 0, s, a);
 }
 
 void launch_lane_selftest(int* out, hipStream_t s) {

@@ -41,7 +41,9 @@ struct ExchArgs {
   double* partials;
   int64_t stride, off_s0, off_s1;
   int n;
-  int64_t n_faces, n_edges;
+  int64_t n_faces, n_edges;             // faces and edges of the range
+  int64_t prim_f0, prim_e0, prim_v0;    // primitive index of the range's
+                                        // first face, edge and vertex
   int64_t face_pts, face_end, edge_end, total;
   double omega, nscale, fill;
 };
@@ -87,8 +89,20 @@ struct CoarseArgs {
   const int64_t* owner;
   const int64_t* copy_ptr;
   const int64_t* copy_slot;
+  const int64_t* blk_dof;  // DoF range of each diagonal block
+  const int64_t* blk_inv;  // offset of each block's inverse in inv
+  const int32_t* row_blk;  // block of each DoF
   double* rhs;
   int64_t ndof;
+};
+
+// Per-segment sums of norm partials: out[s] = sum of p[lo[s] .. hi[s]).
+struct SegArgs {
+  const double* p;
+  const int64_t* lo;
+  const int64_t* hi;
+  double* out;
+  int nseg;
 };
 
 void launch_cell(int dtype, int op, int J, const CellArgs& a, hipStream_t s);
@@ -99,6 +113,7 @@ void launch_flat(int dto, int dti, int fop, const FlatArgs& a, hipStream_t s);
 void launch_sum_partials(const double* p, int64_t count, double* out, bool sq,
                          hipStream_t s);
 void launch_coarse(int dtype, const CoarseArgs& a, hipStream_t s);
+void launch_seg_sum(const SegArgs& a, hipStream_t s);
 void launch_lane_selftest(int* out, hipStream_t s);
 
 }  // namespace ht

@@ -281,6 +281,61 @@ void build_mesh(Mesh& m, const double* xyz, int64_t nv, const int64_t* cells,
       ci.mass_unit = p.mass_unit;
     }
   }
+  set_problems(m, {0, nc}, {max_level});
+}
+
+// Problem partition of the cells.  Faces, edges and vertices are numbered
+// in order of first appearance over the cells, so each problem's primitives
+// form a contiguous run of each kind as long as problems are disjoint; this
+// is checked here.
+void set_problems(Mesh& m, const std::vector<int64_t>& cell_begin,
+                  const std::vector<int>& finest_level) {
+  const int P = (int)cell_begin.size() - 1;
+  if (P < 1 || cell_begin.front() != 0 || cell_begin.back() != m.nc ||
+      (int)finest_level.size() != P)
+    throw Error{HT_ERR_ARG, "bad problem partition"};
+  std::vector<int32_t> prob_of_cell(m.nc);
+  for (int p = 0; p < P; ++p) {
+    if (cell_begin[p + 1] <= cell_begin[p])
+      throw Error{HT_ERR_ARG, "every problem needs at least one cell"};
+    if (p > 0 && finest_level[p] > finest_level[p - 1])
+      throw Error{HT_ERR_ARG, "problems must be sorted by finest level, descending"};
+    for (int64_t c = cell_begin[p]; c < cell_begin[p + 1]; ++c) prob_of_cell[c] = p;
+  }
+  m.nprob = P;
+  m.pcell = cell_begin;
+  auto ranges = [&](int64_t first, int64_t count, std::vector<int64_t>& out) {
+    out.assign(P + 1, 0);
+    int cur = 0;
+    for (int64_t q = 0; q < count; ++q) {
+      const Prim& pr = m.prims[first + q];
+      const int p = prob_of_cell[pr.inc[0].cell];
+      for (const Incidence& I : pr.inc)
+        if (prob_of_cell[I.cell] != p)
+          throw Error{HT_ERR_MESH, "problems of a batch share a primitive"};
+      if (p < cur) throw Error{HT_ERR_MESH, "primitives of a problem are not contiguous"};
+      while (cur < p) out[++cur] = q;
+    }
+    while (cur < P) out[++cur] = count;
+  };
+  ranges(0, m.n_faces, m.pface);
+  ranges(m.n_faces, m.n_edges, m.pedge);
+  ranges(m.n_faces + m.n_edges, m.n_verts, m.pvert);
+  m.act_cells.assign(m.max_level + 1, 0);
+  for (int l = 0; l <= m.max_level; ++l) {
+    int p1 = 0;
+    while (p1 < P && finest_level[p1] >= l) ++p1;
+    m.act_cells[l] = cell_begin[p1];
+  }
+}
+
+Range problem_range(const Mesh& m, int p0, int p1) {
+  Range r;
+  r.c0 = m.pcell[p0]; r.c1 = m.pcell[p1];
+  r.f0 = m.pface[p0]; r.f1 = m.pface[p1];
+  r.e0 = m.pedge[p0]; r.e1 = m.pedge[p1];
+  r.v0 = m.pvert[p0]; r.v1 = m.pvert[p1];
+  return r;
 }
 
 void level_scaled_stencils(const Mesh& m, int level, std::vector<double>& w) {
@@ -457,12 +512,29 @@ void build_coarse_solver(Mesh& m, int level, CoarseSolver& cs) {
     dof_of_slot[s] = id;
     copies[id].push_back(s);
   }
+  // blocks: the DoFs of one problem are contiguous (owner copies lie in the
+  // problem's own cells, which are contiguous in slot order)
+  cs.blk_dof.assign(1, 0);
+  cs.row_blk.assign(N, 0);
+  for (int p = 0; p < m.nprob; ++p) {
+    int64_t d1 = cs.blk_dof.back();
+    while (d1 < N && cs.owner_slot[d1] < m.pcell[p + 1] * L.stride) ++d1;
+    for (int64_t d = cs.blk_dof.back(); d < d1; ++d) cs.row_blk[d] = p;
+    cs.blk_dof.push_back(d1);
+  }
+  cs.blk_inv.assign(m.nprob, 0);
+  int64_t inv_size = 0;
+  for (int p = 0; p < m.nprob; ++p) {
+    const int64_t nb = cs.blk_dof[p + 1] - cs.blk_dof[p];
+    cs.blk_inv[p] = inv_size;
+    inv_size += nb * nb;
+  }
   cs.copy_ptr.assign(N + 1, 0);
   for (int64_t d = 0; d < N; ++d) cs.copy_ptr[d + 1] = cs.copy_ptr[d] + copies[d].size();
   cs.copy_slot.clear();
   for (auto& v : copies) cs.copy_slot.insert(cs.copy_slot.end(), v.begin(), v.end());
   // Rows: each copy contributes its cell's class-partial stencil.
-  std::vector<double> A(N * N, 0.0);
+  std::vector<double> A(inv_size, 0.0);
   const double scale = std::ldexp(1.0, -level);
   for (int64_t c = 0; c < m.nc; ++c) {
     for (int k = 0; k <= n; ++k)
@@ -481,11 +553,19 @@ void build_coarse_solver(Mesh& m, int level, CoarseSolver& cs) {
             if (ii < 0 || jj < 0 || kk < 0 || ii + jj + kk > n) continue;
             const int64_t col = dof_of_slot[c * L.stride + slot_in_cell(L, ii, jj, kk)];
             if (col < 0) continue;  // Dirichlet neighbour: not an unknown
-            A[row * N + col] += w;
+            const int b = cs.row_blk[row];
+            const int64_t d0 = cs.blk_dof[b], nb = cs.blk_dof[b + 1] - d0;
+            A[cs.blk_inv[b] + (row - d0) * nb + (col - d0)] += w;
           }
         }
   }
-  cholesky_inverse(A, N);
+  for (int p = 0; p < m.nprob; ++p) {
+    const int64_t nb = cs.blk_dof[p + 1] - cs.blk_dof[p];
+    if (nb == 0) continue;
+    std::vector<double> blk(A.begin() + cs.blk_inv[p], A.begin() + cs.blk_inv[p] + nb * nb);
+    cholesky_inverse(blk, nb);
+    std::copy(blk.begin(), blk.end(), A.begin() + cs.blk_inv[p]);
+  }
   cs.inv.swap(A);
   cs.ndof = N;
   cs.level = level;

@@ -15,10 +15,17 @@ from tests.conftest import mesh_by_name, oracle_hierarchy
 class Pair:
     """Library mesh + oracle hierarchy built from the same synthetic input."""
 
-    def __init__(self, name: str, max_level: int, min_level: int = 0):
+    def __init__(self, name: str, max_level: int, min_level: int = 0,
+                 arrays=None):
         self.name = name
-        self.H = oracle_hierarchy(name, max_level, min_level)
-        self.m = ht.Mesh(*mesh_by_name(name), min_level, max_level)
+        if arrays is None:
+            self.H = oracle_hierarchy(name, max_level, min_level)
+            arrays = mesh_by_name(name)
+        else:
+            from oracle.mg import Hierarchy
+            self.H = Hierarchy(*arrays, max_level=max_level,
+                               min_level=min_level)
+        self.m = ht.Mesh(*arrays, min_level, max_level)
         self._maps = {}
 
     def S(self, level):

@@ -179,3 +179,34 @@ def test_level_scaling_is_exact(lib):
     base = m.cell_stencils(2)
     for lvl in range(3, 7):
         assert np.array_equal(m.cell_stencils(lvl) * 2 ** (lvl - 2), base)
+
+
+def test_batch_create_and_errors(lib):
+    """Batch creation is host-only: counts add up, bad inputs are refused
+    before any device work."""
+    import ctypes as C
+    from workloads import batch_problems
+    probs = batch_problems(count=5, seed=6, min_level=3, max_level=5)
+    meshes = [ht.Mesh(p.xyz, p.cells, 2, p.level) for p in probs]
+    b = ht.Batch(meshes, [p.level for p in probs])
+    info = b.info()
+    assert info["problems"] == 5
+    assert info["cells"] == sum(len(p.cells) for p in probs)
+    assert info["dofs"] == sum(m.info(p.level)["n_dofs"]
+                               for m, p in zip(meshes, probs))
+    n = len(meshes)
+    arr = (C.c_void_p * n)(*[m._h.value for m in meshes])
+    h = C.c_void_p()
+    bad = (C.c_int * n)(*([9] + [p.level for p in probs[1:]]))
+    assert lib.ht_batch_create(arr, bad, n, C.byref(h)) == _lib.HT_ERR_LEVEL
+    assert lib.ht_batch_create(arr, bad, 0, C.byref(h)) == _lib.HT_ERR_ARG
+    # options are checked before any device call
+    fake = (C.c_void_p * n)(*([256] * n))
+    st = (_lib.SolveStats * n)()
+    o = _lib.SolveOpts(_lib.CycleOpts(2, 2, 2.0 / 3.0, 2), ht.HT_PREC_MIXED,
+                       1e-10, 10, 1)
+    assert lib.ht_batch_solve(b._h, C.byref(o), fake, fake, st, None) == _lib.HT_ERR_ARG
+    o.precision = ht.HT_PREC_F64
+    o.cyc.coarse_level = min(p.level for p in probs) + 1
+    assert lib.ht_batch_solve(b._h, C.byref(o), fake, fake, st, None) == _lib.HT_ERR_LEVEL
+    b.close()
