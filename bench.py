@@ -41,6 +41,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-level", type=int, default=5)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-batch", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run 3 plain device copies of one level vector "
                         "(counter calibration for rocprofv3 --pmc)")
@@ -64,6 +65,63 @@ def measured_traffic(kernel: str):
     if rec.get("sources_sha256") != h.hexdigest() or rec.get("kernel") != kernel:
         return None
     return float(rec["hbm_bytes_per_launch"])
+
+
+def batch_leg(ht, torch):
+    """256 independent small problems (1-24 cells, levels 3-6): one batched
+    solve to 1e-10 against a loop of per-problem solves (both after a
+    warm-up run that captures graphs and builds the coarse solvers)."""
+    from workloads import batch_problems
+    probs = batch_problems(count=256, seed=6, min_level=3, max_level=6)
+    meshes = [ht.Mesh(p.xyz, p.cells, 2, p.level) for p in probs]
+    bs = []
+    for m, p in zip(meshes, probs):
+        g = torch.Generator(device="cuda").manual_seed(1000 + p.index)
+        f = torch.rand(m.n_slots(p.level), dtype=torch.float64, device="cuda",
+                       generator=g) * 2 - 1
+        m.sync(p.level, f)
+        mass = torch.zeros_like(f)
+        m.lumped_mass(p.level, mass)
+        bs.append(mass * f)
+    t0 = time.time()
+    batch = ht.Batch(meshes, [p.level for p in probs])
+    create_s = time.time() - t0
+    info = batch.info()
+
+    def run_batch():
+        us = [torch.zeros_like(b) for b in bs]
+        torch.cuda.synchronize()
+        st = batch.solve(us, bs, rel_tol=1e-10, max_cycles=100)
+        return us, st
+
+    def run_loop():
+        us = [torch.zeros_like(b) for b in bs]
+        torch.cuda.synchronize()
+        t1 = time.time()
+        st = [m.solve(p.level, u, b, ht.HT_PREC_F64, 1e-10, 100)
+              for m, p, u, b in zip(meshes, probs, us, bs)]
+        torch.cuda.synchronize()
+        return us, st, time.time() - t1
+
+    run_batch()
+    ub, stb = run_batch()
+    run_loop()
+    ul, stl, loop_s = run_loop()
+    batch_s = stb[0]["seconds"]
+    diff = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(ub, ul))
+    return {"workload": "256 problems (Kuhn boxes <= 4 cubes, jittered slabs; "
+                        "levels 3-6; seed 6), FP64 V(2,2) to 1e-10",
+            "problems": info["problems"], "cells": info["cells"],
+            "dofs": info["dofs"], "batch_seconds": round(batch_s, 4),
+            "loop_seconds": round(loop_s, 4),
+            "speedup_vs_loop": round(loop_s / batch_s, 2),
+            "solves_per_s": round(info["problems"] / batch_s, 1),
+            "gdofs_solved_per_s": round(info["dofs"] / batch_s / 1e9, 4),
+            "cycles_max": max(x["cycles"] for x in stb),
+            "cycles_equal_to_loop": sum(a["cycles"] == b["cycles"]
+                                        for a, b in zip(stb, stl)),
+            "max_rel_diff_vs_loop": diff,
+            "create_seconds": round(create_s, 3)}
 
 
 def cpu_baseline(level: int, budget_s: float):
@@ -268,6 +326,11 @@ def main():
         log(f"solve kernel breakdown: {json.dumps(breakdown)}")
         solves["kernel_ms"] = breakdown
         out["solve_to_1e-10"] = solves
+
+    if not args.no_batch:
+        log("batched solves of 256 small problems")
+        out["batch"] = batch_leg(ht, torch)
+        log(f"batch: {json.dumps(out['batch'])}")
 
     if not args.no_cpu:
         log(f"CPU oracle baseline at level {args.cpu_level}")
