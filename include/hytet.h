@@ -243,7 +243,7 @@ int ht_batch_solve(ht_batch* batch, const ht_solve_opts* opts,
 /* The stencil kernel runs one wavefront per tile of 64 i-points x R rows,
  * marching in k.  R in {4, 8, 16} trades register pressure against halo
  * re-reads.  ht_set_tile_rows fixes R for (level, dtype); ht_get_tile_rows
- * reports the current choice (default 8). */
+ * reports the current choice (default 4). */
 int ht_set_tile_rows(ht_mesh* mesh, int level, int dtype, int rows);
 int ht_get_tile_rows(const ht_mesh* mesh, int level, int dtype, int* rows);
 /* Autotuner: times every R on the live apply at (level, dtype) on `stream`

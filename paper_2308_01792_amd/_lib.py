@@ -100,6 +100,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         raise RuntimeError(
             f"{path} is missing: build it with "
             "`python -m paper_2308_01792_amd._build` (hipcc, gfx950)")
+    # torch's ROCm build ships its own HIP runtime: load it first so that
+    # the library and torch share one runtime (one device context)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -120,11 +120,13 @@ static T* upload(const std::vector<T>& v) {
 }
 
 static const int kJ[] = {4, 8, 16};
+// untuned tile rows: 4 keeps the FP64 stencil kernels at three waves per SIMD
+static const int kDefaultJ = 4;
 
-// Tile groups of the stencil kernel: 62 output i x (4 waves x J rows).
+// Tile groups of the stencil kernel: 62 output i x (kCellWaves x J rows).
 static std::vector<int2> make_tiles(int n, int J) {
   std::vector<int2> t;
-  const int G = 4 * J;
+  const int G = kCellWaves * J;
   for (int tj = 0; G * tj <= n; ++tj)
     for (int ti = 0; 62 * ti + G * tj <= n; ++ti) t.push_back(make_int2(62 * ti, G * tj));
   return t;
@@ -141,7 +143,7 @@ static int64_t partials_needed(const ht_mesh* h, int level) {
   const Mesh& m = h->m;
   const int n = 1 << level;
   int64_t cell_blocks = 0;
-  for (int J : kJ) cell_blocks = std::max<int64_t>(cell_blocks, 4 * m.nc * (int64_t)make_tiles(n, J).size());
+  for (int J : kJ) cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J).size());
   const int64_t fp = n_tri(n - 2), total = m.n_faces * fp + m.n_edges * std::max(n - 1, 0) + m.n_verts;
   const int64_t exch_blocks = (total + 255) / 256;
   const int64_t elem_blocks = m.nc * (int64_t)make_walk_tiles(n).size();
@@ -250,7 +252,7 @@ static void check_launch() {
 static int choose_J(ht_mesh* h, int level, int dtype) {
   auto it = h->tuned_J.find({level, dtype});
   if (it != h->tuned_J.end()) return it->second;
-  return 8;
+  return kDefaultJ;
 }
 
 // Stencil-kernel arguments over the cells of R: every per-cell array is
@@ -323,17 +325,15 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
     check_launch();
   }
   ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
-                          m.d_partials + 4 * ca.nblocks, R);
+                          m.d_partials + kCellWaves * ca.nblocks, R);
   if (op == OP_RESID) ea.u = x;
-  ea.x = x;
-  ea.w = level_weights(h, level, dtype);
   if (ea.total > 0) {
     Prof p(h, "exchange", s);
     launch_exchange(dtype, op, ea, s);
     check_launch();
   }
   if (op == OP_RESID && want_norm) {
-    const int64_t cnt = 4 * ca.nblocks + (ea.total + 255) / 256;
+    const int64_t cnt = kCellWaves * ca.nblocks + (ea.total + 255) / 256;
     Prof p(h, "norm_sum", s);
     launch_sum_partials(m.d_partials, cnt, m.d_scalar + scalar_slot, true, s);
     check_launch();
@@ -1314,7 +1314,7 @@ int ht_get_tile_rows(const ht_mesh* h, int level, int dtype, int* rows) {
     check_level(h->m, level);
     check_dtype(dtype);
     auto it = h->tuned_J.find({level, dtype});
-    *rows = it == h->tuned_J.end() ? 8 : it->second;
+    *rows = it == h->tuned_J.end() ? kDefaultJ : it->second;
   });
 }
 
@@ -1357,7 +1357,7 @@ int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
     HT_CHECK_HIP(hipEventCreate(&e1));
     const bool was_profiling = h->m.profiling;
     h->m.profiling = false;
-    int best = 8;
+    int best = kDefaultJ;
     float best_ms = 1e30f;
     try {
       for (int J : kJ) {

@@ -119,6 +119,11 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r,
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
 
+// In-face offsets of the face i = 0 (class 1) and of the slanted face
+// i + j + k = n (class 8), as indices into the 15-offset list.
+__constant__ int kInFace1[7] = {0, 3, 4, 5, 6, 11, 12};
+__constant__ int kInFace8[7] = {0, 7, 8, 9, 10, 11, 12};
+
 // One wave = one tile of 64 consecutive i (62 outputs, one halo lane on each
 // side) and J rows j0..j0+J-1, marching k upwards with the planes k-1, k,
 // k+1 of rows j0-1..j0+J in registers; i +- 1 neighbours come from DPP.  The
@@ -127,11 +132,11 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r,
 //
 // Points on the cell's faces get the cell's partial row.  On rows with
 // j >= 1, k >= 1 and line end e >= 2 ("generic" rows) only two lanes are
-// surface points: i = 0 (face i = 0) and i = e (slanted face).  They store
-// the interior formula evaluated with zero outside the closure; the cell's
-// exact partial row differs from it by a 7-term sum over the in-face offsets
-// only, which the ghost-exchange kernel adds.  Rows with j == 0, k == 0 or
-// e <= 1 take exact per-lane class weights from LDS.
+// surface points: i = 0 (face i = 0) and i = e (slanted face).  The interior
+// formula evaluated with zero outside the closure differs from their exact
+// partial row by a 7-term sum over the in-face offsets only, which the one
+// tile holding the lane adds.  Rows with j == 0, k == 0 or e <= 1 take
+// exact per-lane class weights from LDS.
 //
 // OP_RESTRICT runs the same march over a fine residual with the fixed
 // stencil of P^T (1 at the centre, 1/2 on the 14 edge neighbours) and
@@ -140,12 +145,16 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r,
 // every fine micro-vertex is restricted by exactly one cell and shared coarse
 // points receive partial sums for the ghost exchange.
 template <typename T, int OP, int J>
-__global__ __launch_bounds__(256) void k_cell(CellArgs a) {
+__global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   constexpr bool RESTR = (OP == OP_RESTRICT);
   __shared__ T wtab[16 * 15];
-  // A workgroup is four waves on four vertically adjacent tiles of one cell
-  // (rows j0 .. j0 + 4J - 1): the waves march in near lockstep on one CU,
-  // so each wave's halo rows are its neighbours' rows, fetched once.
+  // in-face parts of (class weights - interior weights) on the faces i = 0
+  // (class 1, offsets 0 3 4 5 6 11 12) and i + j + k = n (class 8, offsets
+  // 0 7 8 9 10 11 12), in that order
+  __shared__ T dwtab[14];
+  // A workgroup is kCellWaves waves on vertically adjacent tiles of one cell
+  // (rows j0 .. j0 + kCellWaves J - 1): the waves march in near lockstep on
+  // one CU, so each wave's halo rows are its neighbours' rows, fetched once.
   // XCD-aware block order: block b runs on XCD b % 8; give each XCD a
   // contiguous run of (cell, tile group) work so neighbouring groups share
   // an L2.
@@ -159,7 +168,7 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
   // wave index, uniform over the wave: say so, so that the row bookkeeping
   // derived from it lives in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t w = wb * 4 + wave;  // partial-sum slot of this wave
+  const int64_t w = wb * kCellWaves + wave;  // partial-sum slot of this wave
   const int i0 = tile.x, j0 = tile.y + wave * J;
   const int n = a.n;
   const int64_t bytes = a.stride * (int64_t)sizeof(T);
@@ -174,7 +183,13 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
   unsigned own16 = 0;
   if (!RESTR) {
     const T* wc = (const T*)a.w + cell * 240;
-    for (int t = threadIdx.x; t < 240; t += 256) wtab[t] = wc[t];
+    for (int t = threadIdx.x; t < 240; t += 64 * kCellWaves) wtab[t] = wc[t];
+    __syncthreads();
+    if (threadIdx.x < 14) {
+      const int t = threadIdx.x;
+      const int d = t < 7 ? kInFace1[t] : kInFace8[t - 7];
+      dwtab[t] = wtab[(t < 7 ? 1 : 8) * 15 + d] - wtab[d];
+    }
     __syncthreads();
     // interior weights from LDS: they stay in VGPRs and leave the scalar
     // registers to the row bookkeeping
@@ -197,34 +212,41 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
   // block base mb(j) (element of i = 0 if it were stored there), S0 and S1
   // entries sa(j), sb(j); consecutive rows differ by the main-block row
   // length (n-1-kk-j) and by 1 in S0/S1.
-  auto plane_offsets = [&](int kk, unsigned (&o)[J + 2]) {
-    const int w1_ = n - 1;
-    int mb = (int)(n_tet(w1_) - n_tet(w1_ - kk)) - 1;
-    int sa = off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - kk));
-    int sb = off_s1 + (int)(n_tri(n) - n_tri(n - kk));
-    const int jf = j0 - 1;
-    if (jf > 0) {
-      mb += jf * (w1_ - kk) - jf * (jf - 1) / 2;
-      sa += jf;
-      sb += jf;
-    }
+  // Scalar cursor over the planes to load: element bases of plane ck in the
+  // main block (minus one), in S0 and in S1 (closure layout of index.hpp).
+  // Each plane advances them by its own size, so no plane recomputes the
+  // tetrahedral numbers.
+  const int wm = n - 1;  // width of the main block's polytope
+  int ck = 0, cmb = -1, csa = off_s0, csb = off_s1;
+  auto advance = [&]() {
+    const int wk = wm - ck;
+    cmb += wk > 0 ? wk * (wk + 1) / 2 : 0;
+    csa += n + 1 - ck;
+    csb += n - ck;
+    ++ck;
+  };
+  // Byte offsets of this lane's point in rows j0-1 .. j0+J of plane ck
+  // (HT_OOB outside the closure), then move the cursor to the next plane.
+  auto plane_offsets = [&](unsigned (&o)[J + 2]) {
+    const int kk = ck, wk = wm - kk;
+    const int jf = j0 - 1, js = jf > 0 ? jf : 0;
+    int mb = cmb + js * wk - js * (js - 1) / 2;
+    int sa = csa + js, sb = csb + js;
 #pragma unroll
     for (int r = 0; r < J + 2; ++r) {
       const int j = jf + r;
       const int e = n - j - kk;
-      unsigned off = HT_OOB;
-      if (j >= 0 && e >= 0 && kk <= n) {
-        int el = (i == e) ? sb : mb + i;
-        el = is0 ? sa : el;
-        off = ((unsigned)i <= (unsigned)e) ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB;
-      }
-      o[r] = off;
-      if (j >= 0) {
-        mb += w1_ - kk - j;
-        ++sa;
-        ++sb;
-      }
+      const bool row_ok = j >= 0 && e >= 0;
+      int el = (i == e) ? sb : mb + i;
+      el = is0 ? sa : el;
+      o[r] = (row_ok && (unsigned)i <= (unsigned)e) ? (unsigned)el * (unsigned)sizeof(T)
+                                                    : HT_OOB;
+      const bool inc = j >= 0;
+      mb += inc ? wk - j : 0;
+      sa += inc ? 1 : 0;
+      sb += inc ? 1 : 0;
     }
+    advance();
   };
   // restriction: fine points not owned by this cell read as zero
   auto mask_plane = [&](int kk, T (&v)[J + 2]) {
@@ -246,7 +268,7 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
   auto step = [&](int k, T (&pm)[J + 2], T (&pc)[J + 2], T (&pp)[J + 2],
                   T (&pn)[J + 2], unsigned (&oc)[J + 2], unsigned (&op)[J + 2],
                   unsigned (&on)[J + 2], T (&bc)[J], T (&bp)[J]) {
-    plane_offsets(k + 2, on);
+    plane_offsets(on);
 #pragma unroll
     for (int r = 0; r < J + 2; ++r) bload(pn[r], rx, on[r]);
     if (NEED_B) {
@@ -262,14 +284,14 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
       if (RESTR && (rr & 1)) continue;
       if (e < i0) continue;
       const T c = pc[rr + 1];
-      const T v1 = lane_next(c), v2 = lane_prev(c);
-      const T v3 = pc[rr + 2], v4 = pc[rr];
-      const T v5 = pp[rr + 1], v6 = pm[rr + 1];
-      const T v7 = lane_prev(pc[rr + 2]), v8 = lane_next(pc[rr]);
-      const T v9 = lane_prev(pp[rr + 1]), v10 = lane_next(pm[rr + 1]);
-      const T v11 = pp[rr], v12 = pm[rr + 2];
-      const T v13 = lane_next(pp[rr]), v14 = lane_prev(pm[rr + 2]);
       if (RESTR) {
+        const T v1 = lane_next(c), v2 = lane_prev(c);
+        const T v3 = pc[rr + 2], v4 = pc[rr];
+        const T v5 = pp[rr + 1], v6 = pm[rr + 1];
+        const T v7 = lane_prev(pc[rr + 2]), v8 = lane_next(pc[rr]);
+        const T v9 = lane_prev(pp[rr + 1]), v10 = lane_next(pm[rr + 1]);
+        const T v11 = pp[rr], v12 = pm[rr + 2];
+        const T v13 = lane_next(pp[rr]), v14 = lane_prev(pm[rr + 2]);
         // P^T at the even fine point (i, j, k) -> coarse (i, j, k) / 2
         const T nb14 = ((v1 + v2) + (v3 + v4)) + ((v5 + v6) + (v7 + v8)) +
                        ((v9 + v10) + (v11 + v12)) + (v13 + v14);
@@ -285,15 +307,28 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
         bstore(val, ry, ok ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB);
         continue;
       }
+      // Interior weights are the same on every lane, and a lane shift is
+      // linear: the four terms taken at i + 1 (offsets 1, 8, 10, 13) are
+      // summed first and shifted once, likewise the four at i - 1 (offsets
+      // 2, 7, 9, 14): 2 shifts per row instead of 8.
+      const T sn = fma(w13, pp[rr], fma(w10, pm[rr + 1], fma(w8, pc[rr], w1 * c)));
+      const T sp = fma(w14, pm[rr + 2], fma(w9, pp[rr + 1], fma(w7, pc[rr + 2], w2 * c)));
       T acc = w0 * c;
-      acc = fma(w1, v1, acc); acc = fma(w2, v2, acc); acc = fma(w3, v3, acc);
-      acc = fma(w4, v4, acc); acc = fma(w5, v5, acc); acc = fma(w6, v6, acc);
-      acc = fma(w7, v7, acc); acc = fma(w8, v8, acc); acc = fma(w9, v9, acc);
-      acc = fma(w10, v10, acc); acc = fma(w11, v11, acc);
-      acc = fma(w12, v12, acc); acc = fma(w13, v13, acc);
-      acc = fma(w14, v14, acc);
+      acc = fma(w3, pc[rr + 2], acc); acc = fma(w4, pc[rr], acc);
+      acc = fma(w5, pp[rr + 1], acc); acc = fma(w6, pm[rr + 1], acc);
+      acc = fma(w11, pp[rr], acc); acc = fma(w12, pm[rr + 2], acc);
+      acc += lane_next(sn);
+      acc += lane_prev(sp);
       bool surf;
       if (j == 0 || k == 0 || e <= 1) {
+        // per-lane class weights: shift every neighbour individually
+        const T v1 = lane_next(c), v2 = lane_prev(c);
+        const T v3 = pc[rr + 2], v4 = pc[rr];
+        const T v5 = pp[rr + 1], v6 = pm[rr + 1];
+        const T v7 = lane_prev(pc[rr + 2]), v8 = lane_next(pc[rr]);
+        const T v9 = lane_prev(pp[rr + 1]), v10 = lane_next(pm[rr + 1]);
+        const T v11 = pp[rr], v12 = pm[rr + 2];
+        const T v13 = lane_next(pp[rr]), v14 = lane_prev(pm[rr + 2]);
         const int cls = (int)is0 | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3);
         const T* wt = wtab + cls * 15;
         T sacc = wt[0] * c;
@@ -307,10 +342,31 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
         acc = sacc;
         surf = cls != 0;
       } else {
-        // generic row: the lanes i = 0 and i = e hold the cell's interior
-        // formula with zero outside the closure; the ghost exchange adds
-        // their in-face correction.
+        // generic row: the interior formula with zero outside the closure is
+        // the cell's partial row everywhere except at i = 0 and i = e, where
+        // the in-face weights differ.  Only the tile holding that lane adds
+        // the difference (a uniform branch).
         surf = is0 || (i == e);
+        // Residual and Jacobi hold b as well: there the weights are read
+        // where used, indexed by k >> 30 (always 0, k < 2^30) so that they
+        // are not hoisted out of the plane loop into 28 registers held for
+        // the whole march (which would cost a wave per SIMD).  The apply has
+        // the registers to spare and keeps them hoisted.
+        const T* dw = dwtab + (NEED_B ? (k >> 30) : 0);
+        if (i0 == 0) {
+          T c1 = dw[0] * c;
+          c1 = fma(dw[1], pc[rr + 2], c1); c1 = fma(dw[2], pc[rr], c1);
+          c1 = fma(dw[3], pp[rr + 1], c1); c1 = fma(dw[4], pm[rr + 1], c1);
+          c1 = fma(dw[5], pp[rr], c1); c1 = fma(dw[6], pm[rr + 2], c1);
+          acc += is0 ? c1 : (T)0;
+        }
+        if (e >= i0 && e <= i0 + 61) {
+          T c8 = dw[7] * c;
+          c8 = fma(dw[12], pp[rr], c8); c8 = fma(dw[13], pm[rr + 2], c8);
+          c8 += lane_next(fma(dw[9], pc[rr], dw[11] * pm[rr + 1]));
+          c8 += lane_prev(fma(dw[8], pc[rr + 2], dw[10] * pp[rr + 1]));
+          acc += (i == e) ? c8 : (T)0;
+        }
       }
       const unsigned so = oc[rr + 1] | out_mask;
       T out = acc;
@@ -332,8 +388,8 @@ __global__ __launch_bounds__(256) void k_cell(CellArgs a) {
   T PA[J + 2], PB[J + 2], PC[J + 2], PD[J + 2];
   unsigned OA[J + 2], OB[J + 2], OC[J + 2], OD[J + 2];
   T BA[J], BB[J];
-  plane_offsets(0, OB);
-  plane_offsets(1, OC);
+  plane_offsets(OB);
+  plane_offsets(OC);
 #pragma unroll
   for (int r = 0; r < J + 2; ++r) {
     PA[r] = (T)0;
@@ -375,10 +431,6 @@ __device__ __forceinline__ void tri_decode(int64_t p, int m, int& a, int& b) {
   a = (int)(p - start(bb));
 }
 
-// In-face offsets of the face i = 0 (class 1) and of the slanted face
-// i + j + k = n (class 8), as indices into the 15-offset list.
-__constant__ int kInFace1[7] = {0, 3, 4, 5, 6, 11, 12};
-__constant__ int kInFace8[7] = {0, 7, 8, 9, 10, 11, 12};
 
 // One thread per micro-vertex shared by several cells (face interiors, then
 // edge interiors, then vertices).  Sums the partial rows of all incident
@@ -444,25 +496,6 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
         const DevInc I = local_q(q, i, j, k);
         const int64_t cb = (int64_t)I.cell * L.stride;
         sum += y[cb + slot_of(L, i, j, k)];
-        // The stencil kernel left the interior formula at face points of
-        // faces i = 0 / i+j+k = n on its generic rows (e >= 2): add the
-        // in-face part of (class weights - interior weights) . x.
-        const bool gen1 = I.cls == 1 && n - j - k >= 2;
-        const bool gen8 = I.cls == 8 && i >= 2;
-        if ((OP == OP_APPLY || OP == OP_RESID || OP == OP_JACOBI) && (gen1 || gen8)) {
-          const T* wc = (const T*)a.w + (int64_t)I.cell * 240;
-          const T* xc = (const T*)a.x + cb;
-          const int* dl = gen1 ? kInFace1 : kInFace8;
-          T corr = (T)0;
-#pragma unroll
-          for (int m = 0; m < 7; ++m) {
-            int di, dj, dk;
-            stencil_offset(dl[m], di, dj, dk);
-            const T dw = wc[I.cls * 15 + dl[m]] - wc[dl[m]];
-            corr += dw * xc[slot_of(L, i + di, j + dj, k + dk)];
-          }
-          sum += corr;
-        }
       }
       T val;
       if (P.boundary) {
@@ -819,9 +852,9 @@ template <typename T, int OP>
 static void launch_cell_t(const CellArgs& a, int J, hipStream_t s) {
   const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8));
   switch (J) {
-    case 4: hipLaunchKernelGGL((k_cell<T, OP, 4>), grid, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_cell<T, OP, 8>), grid, dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_cell<T, OP, 16>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_cell<T, OP, 4>), grid, dim3(64 * kCellWaves), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_cell<T, OP, 8>), grid, dim3(64 * kCellWaves), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_cell<T, OP, 16>), grid, dim3(64 * kCellWaves), 0, s, a); break;
     default: throw Error{HT_ERR_ARG, "tile rows must be 4, 8 or 16"};
   }
 }
@@ -857,10 +890,7 @@ void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
   if (op != OP_APPLY && op != OP_RESID && op != OP_JACOBI && op != OP_SYNC &&
       op != OP_FILL && op != OP_RESTRICT)
     throw Error{HT_ERR_ARG, "unknown exchange operation"};
-  // the stencil epilogues read the operand and the stencil table for the
-  // in-face corrections, Jacobi/residual also u and b
-  if ((op == OP_APPLY || op == OP_RESID || op == OP_JACOBI) && (!a.x || !a.w))
-    throw Error{HT_ERR_ARG, "exchange after a stencil pass needs x and w"};
+  // the residual and Jacobi epilogues read u and b at the owner copy
   if ((op == OP_RESID || op == OP_JACOBI) && (!a.u || !a.b))
     throw Error{HT_ERR_ARG, "exchange for residual/Jacobi needs u and b"};
   if (dtype == HT_F64) launch_exchange_t<double>(op, a, s);

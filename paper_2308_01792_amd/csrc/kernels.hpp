@@ -13,6 +13,12 @@ enum { EOP_ZERO_GUESS = 0, EOP_MASS = 1, EOP_ZERO_INTERIOR = 2, EOP_DOT = 3,
        EOP_FLAGS = 4, EOP_COORDS = 5 };
 enum { FOP_COPY = 0, FOP_ADD = 1, FOP_ZERO = 2 };
 enum { kMaxInc = 128 };  // incident cells per shared primitive (checked)
+// Waves per stencil-kernel workgroup, stacked in j on one cell: a group
+// covers kCellWaves x J rows and loads 2 halo rows for all of them.
+#ifndef HT_CELL_WAVES
+#define HT_CELL_WAVES 4
+#endif
+enum { kCellWaves = HT_CELL_WAVES };
 
 struct CellArgs {
   const void* x;        // operand (u for residual / Jacobi)
@@ -32,8 +38,6 @@ struct CellArgs {
 
 struct ExchArgs {
   void* y;
-  const void* x;        // operand of the stencil pass (face corrections)
-  const void* w;        // level-scaled class stencils [nc][16][15]
   const void* u;
   const void* b;
   const DevPrim* prim;
