@@ -15,6 +15,19 @@
 
 namespace ht {
 
+// 32-bit index arithmetic for device code.  A cell block holds fewer than
+// 2^31 elements up to level 10 (w (w+1) (w+2) <= 1025 * 1026 * 1027 <
+// 2^31), so the tetrahedral and triangular numbers of index.hpp are formed
+// without 64-bit multiplies and divisions.
+__device__ __forceinline__ int tet32(int w) { return w <= 0 ? 0 : w * (w + 1) * (w + 2) / 6; }
+__device__ __forceinline__ int tri32(int w) { return w <= 0 ? 0 : w * (w + 1) / 2; }
+__device__ __forceinline__ int tw32(int w, int i, int j, int k) {
+  return tet32(w) - tet32(w - k) + tri32(w - k) - tri32(w - k - j) + i;
+}
+__device__ __forceinline__ int t2w32(int w, int j, int k) {
+  return tri32(w) - tri32(w - k) + j;
+}
+
 // ------------------------------------------------------- lane exchange --
 // DPP wave shifts (GFX9 family): wave_shr:1 gives lane L the value of lane
 // L-1, wave_shl:1 the value of lane L+1.  With bound_ctrl set, lanes shifted
@@ -74,9 +87,9 @@ __device__ __forceinline__ RowBase row_base(const Lay& L, int j, int k) {
   RowBase r;
   const int n = L.n;
   r.e = n - j - k;
-  r.s0 = (int32_t)(L.off_s0 + t2_w(n + 1, j, k));
-  r.s1 = (int32_t)(L.off_s1 + t2_w(n, j, k));
-  r.m = (int32_t)t_w(n - 1, 0, j, k);
+  r.s0 = (int32_t)(L.off_s0 + t2w32(n + 1, j, k));
+  r.s1 = (int32_t)(L.off_s1 + t2w32(n, j, k));
+  r.m = (int32_t)tw32(n - 1, 0, j, k);
   return r;
 }
 __device__ __forceinline__ int32_t row_slot(const RowBase& r, int i) {
@@ -84,9 +97,9 @@ __device__ __forceinline__ int32_t row_slot(const RowBase& r, int i) {
 }
 __device__ __forceinline__ int64_t slot_of(const Lay& L, int i, int j, int k) {
   const int n = L.n;
-  if (i == 0) return L.off_s0 + t2_w(n + 1, j, k);
-  if (i + j + k == n) return L.off_s1 + t2_w(n, j, k);
-  return t_w(n - 1, i - 1, j, k);
+  if (i == 0) return L.off_s0 + t2w32(n + 1, j, k);
+  if (i + j + k == n) return L.off_s1 + t2w32(n, j, k);
+  return tw32(n - 1, i - 1, j, k);
 }
 
 template <typename T>
@@ -297,9 +310,9 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
                        ((v9 + v10) + (v11 + v12)) + (v13 + v14);
         const T val = fma((T)0.5, nb14, c);
         const int nc = n >> 1, jc = j >> 1, kc = k >> 1, ec = nc - jc - kc;
-        const int mbc = (int)t_w(nc - 1, 0, jc, kc) - 1;
-        const int sac = (int)a.off_s0_out + (int)t2_w(nc + 1, jc, kc);
-        const int sbc = (int)a.off_s1_out + (int)t2_w(nc, jc, kc);
+        const int mbc = (int)tw32(nc - 1, 0, jc, kc) - 1;
+        const int sac = (int)a.off_s0_out + (int)t2w32(nc + 1, jc, kc);
+        const int sbc = (int)a.off_s1_out + (int)t2w32(nc, jc, kc);
         const int ic = i >> 1;
         int el = (ic == ec) ? sbc : mbc + ic;
         el = (ic == 0) ? sac : el;
@@ -535,9 +548,9 @@ __device__ __forceinline__ void walk_tile(const Lay& L, int i0, int j0, int i,
   const int n = L.n, w1 = n - 1;
   const int kmax = n - i0 - j0;
   for (int k = 0; k <= kmax; ++k) {
-    int mb = (int)(n_tet(w1) - n_tet(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
-    int sa = (int)L.off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - k)) + j0;
-    int sb = (int)L.off_s1 + (int)(n_tri(n) - n_tri(n - k)) + j0;
+    int mb = (int)(tet32(w1) - tet32(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
+    int sa = (int)L.off_s0 + (int)(tri32(n + 1) - tri32(n + 1 - k)) + j0;
+    int sb = (int)L.off_s1 + (int)(tri32(n) - tri32(n - k)) + j0;
 #pragma unroll
     for (int r = 0; r < kWalkRows; ++r) {
       const int j = j0 + r;
@@ -579,9 +592,9 @@ __device__ __forceinline__ CRow crow(const Lay& L, int j, int k) {
   const int n = L.n;
   CRow r;
   r.e = n - j - k;
-  r.mb = (int)t_w(n - 1, 0, j, k) - 1;
-  r.sa = (int)L.off_s0 + (int)t2_w(n + 1, j, k);
-  r.sb = (int)L.off_s1 + (int)t2_w(n, j, k);
+  r.mb = (int)tw32(n - 1, 0, j, k) - 1;
+  r.sa = (int)L.off_s0 + (int)t2w32(n + 1, j, k);
+  r.sb = (int)L.off_s1 + (int)t2w32(n, j, k);
   return r;
 }
 __device__ __forceinline__ void parity_dir(int p, int& di, int& dj, int& dk) {
@@ -612,9 +625,9 @@ __global__ __launch_bounds__(64) void k_prolong(XferArgs a) {
     // all loads of the plane's rows first, then the updates
     unsigned ou[kWalkRows], oa[kWalkRows], ob[kWalkRows];
     bool za[kWalkRows], zb[kWalkRows];
-    int mb = (int)(n_tet(w1) - n_tet(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
-    int sa = (int)Lf.off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - k)) + j0;
-    int sb = (int)Lf.off_s1 + (int)(n_tri(n) - n_tri(n - k)) + j0;
+    int mb = (int)(tet32(w1) - tet32(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
+    int sa = (int)Lf.off_s0 + (int)(tri32(n + 1) - tri32(n + 1 - k)) + j0;
+    int sb = (int)Lf.off_s1 + (int)(tri32(n) - tri32(n - k)) + j0;
 #pragma unroll
     for (int r = 0; r < kWalkRows; ++r) {
       const int j = j0 + r;
@@ -690,9 +703,9 @@ __global__ __launch_bounds__(64) void k_elem(ElemArgs a) {
   for (int k = 0; k <= kmax; ++k) {
     unsigned off[kWalkRows];
     int cl[kWalkRows], elr[kWalkRows];
-    int mb = (int)(n_tet(w1) - n_tet(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
-    int sa = (int)L.off_s0 + (int)(n_tri(n + 1) - n_tri(n + 1 - k)) + j0;
-    int sb = (int)L.off_s1 + (int)(n_tri(n) - n_tri(n - k)) + j0;
+    int mb = (int)(tet32(w1) - tet32(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
+    int sa = (int)L.off_s0 + (int)(tri32(n + 1) - tri32(n + 1 - k)) + j0;
+    int sb = (int)L.off_s1 + (int)(tri32(n) - tri32(n - k)) + j0;
 #pragma unroll
     for (int r = 0; r < kWalkRows; ++r) {
       const int j = j0 + r;
