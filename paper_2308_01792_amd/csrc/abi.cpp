@@ -310,8 +310,9 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
   return a;
 }
 
-// One operator pass (cell kernel + ghost exchange).  For OP_RESID the norm
-// of the result lands in m.d_scalar[slot] (device) when want_norm.
+// One operator pass (cell kernel + ghost exchange).  For OP_RESID and
+// OP_JACOBI the norm of b - A x (x: the operand) lands in m.d_scalar[slot]
+// (device) when want_norm.
 static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
                     void* y, const void* b, double omega, hipStream_t s,
                     bool want_norm, int scalar_slot, const Range& R) {
@@ -332,7 +333,7 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
     launch_exchange(dtype, op, ea, s);
     check_launch();
   }
-  if (op == OP_RESID && want_norm) {
+  if ((op == OP_RESID || op == OP_JACOBI) && want_norm) {
     const int64_t cnt = kCellWaves * ca.nblocks + (ea.total + 255) / 256;
     Prof p(h, "norm_sum", s);
     launch_sum_partials(m.d_partials, cnt, m.d_scalar + scalar_slot, true, s);
@@ -512,17 +513,19 @@ static void* sweeps(ht_mesh* h, int level, int dtype, double omega, int count,
 }
 
 // V(nu1, nu2) on `level`: iterate in u (or t), returns the buffer with the
-// new iterate.  zero_guess: the incoming iterate is zero.
+// new iterate.  zero_guess: the incoming iterate is zero.  first_done: the
+// first pre-smoothing sweep has already been made from u into t.
 static void* vcycle_impl(ht_mesh* h, int level, int dtype,
                          const ht_cycle_opts& o, void* u, void* t,
-                         const void* b, bool zero_guess, hipStream_t s) {
+                         const void* b, bool zero_guess, hipStream_t s,
+                         bool first_done = false) {
   if (level == o.coarse_level) {
     coarse_fast(h, level, dtype, b, u, s);
     return u;
   }
-  void* cur = u;
-  void* other = t;
-  int todo = o.nu1;
+  void* cur = first_done ? t : u;
+  void* other = first_done ? u : t;
+  int todo = first_done ? o.nu1 - 1 : o.nu1;
   if (zero_guess) {
     if (todo > 0) {
       zero_guess_sweep(h, level, dtype, o.omega, cur, b, s, full_range(h->m));
@@ -1038,7 +1041,24 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
     int k = 0;
     const bool mixed = o->precision == HT_PREC_MIXED;
     LevelWork* w32 = mixed ? &work(h, level, HT_F32) : nullptr;
+    // FP64 cycles: the first Jacobi sweep of the next cycle (out of place,
+    // u -> t) also yields |b - A u| of the iterate it starts from, so each
+    // cycle's graph ends with that sweep instead of a separate residual
+    // pass; when the norm meets the tolerance the sweep is discarded and u
+    // is the result.
+    const bool lag = !mixed && o->cyc.nu1 > 0 && level > o->cyc.coarse_level;
+    auto first_sweep = [&](hipStream_t ss) {
+      op_pass(h, level, HT_F64, OP_JACOBI, u, w64.t, b, o->cyc.omega, ss, true, 0);
+      HT_CHECK_HIP(hipMemcpyAsync(h->m.h_scalar, h->m.d_scalar, sizeof(double),
+                                  hipMemcpyDeviceToHost, ss));
+    };
     auto step = [&](hipStream_t ss) {
+      if (lag) {
+        void* res = vcycle_impl(h, level, HT_F64, o->cyc, u, w64.t, b, false, ss, true);
+        if (res != u) flat(h, level, HT_F64, HT_F64, FOP_COPY, u, res, ss);
+        first_sweep(ss);
+        return;
+      }
       if (!mixed) {
         vcycle_top(h, level, HT_F64, o->cyc, u, b, false, ss);
         op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, ss, true, 0);
@@ -1061,6 +1081,10 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
     for (int l = o->cyc.coarse_level; l <= level; ++l) {
       work(h, l, HT_F64);
       if (mixed) work(h, l, HT_F32);
+    }
+    if (lag && rel > o->rel_tol && k < o->max_cycles && std::isfinite(rel)) {
+      first_sweep(s);
+      HT_CHECK_HIP(hipStreamSynchronize(s));
     }
     while (rel > o->rel_tol && k < o->max_cycles && std::isfinite(rel)) {
       if (o->use_graph) run_graph(h, key.str(), step, s);

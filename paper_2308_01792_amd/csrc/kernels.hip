@@ -385,13 +385,16 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
       T out = acc;
       if (NEED_B) {
         const T bval = bc[rr];
+        // both epilogues form r = b - A u and add |r|^2 of the points this
+        // wave finishes to the norm partials (a Jacobi sweep thereby also
+        // yields the residual norm of the iterate it starts from)
+        const T r = bval - acc;
+        const bool counted = !surf && so < HT_OOB;
+        nsq += counted ? (double)r * (double)r : 0.0;
         if (OP == OP_RESID) {
-          const T r = bval - acc;
           out = surf ? acc : r;
-          const bool counted = !surf && so < HT_OOB;
-          nsq += counted ? (double)r * (double)r : 0.0;
         } else {
-          out = surf ? acc : fma(omega_invd, bval - acc, c);
+          out = surf ? acc : fma(omega_invd, r, c);
         }
       }
       bstore(out, ry, so);
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
     if (k + 3 > kmax) break;
     step(k + 3, PD, PA, PB, PC, OA, OB, OC, BB, BA);
   }
-  if (OP == OP_RESID) {
+  if (NEED_B) {
     nsq = wave_sum(nsq);
     if (lane == 0) a.partials[w] = nsq;
   }
@@ -518,7 +521,9 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
         nsq = (double)val * (double)val;
       } else if (OP == OP_JACOBI) {
         const T invd = (T)(a.nscale * P.inv_diag_unit);
-        val = ((const T*)a.u)[s0] + (T)a.omega * invd * (((const T*)a.b)[s0] - sum);
+        const T r = ((const T*)a.b)[s0] - sum;
+        nsq = (double)r * (double)r;
+        val = ((const T*)a.u)[s0] + (T)a.omega * invd * r;
       } else {
         val = sum;
       }
@@ -526,7 +531,7 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       for (int q = 1; q < cnt; ++q) y[slot_q(q)] = val;
     }
   }
-  if (OP == OP_RESID) {
+  if (OP == OP_RESID || OP == OP_JACOBI) {
     __shared__ double red[4];
     nsq = wave_sum(nsq);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nsq;
