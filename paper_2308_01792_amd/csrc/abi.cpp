@@ -310,30 +310,35 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
   return a;
 }
 
-// One operator pass (cell kernel + ghost exchange).  For OP_RESID and
-// OP_JACOBI the norm of b - A x (x: the operand) lands in m.d_scalar[slot]
-// (device) when want_norm.
+// One operator pass (cell kernel + ghost exchange).  For OP_RESID,
+// OP_RESID32 and OP_JACOBI the norm of b - A x (x: the operand) lands in
+// m.d_scalar[slot] (device) when want_norm.  OP_RESID32 (FP64 only) delivers
+// the residual in the FP32 vector y32 and uses y as FP64 scratch.
 static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
                     void* y, const void* b, double omega, hipStream_t s,
-                    bool want_norm, int scalar_slot, const Range& R) {
+                    bool want_norm, int scalar_slot, const Range& R,
+                    void* y32 = nullptr) {
   Mesh& m = h->m;
   if (R.empty()) return;
   const int J = choose_J(h, level, dtype);
   CellArgs ca = cell_args(h, level, dtype, J, x, y, b, omega, R);
+  ca.y32 = at_cell(y32, R.c0, level, HT_F32);
   {
-    Prof p(h, op == OP_APPLY ? "cell_apply" : op == OP_RESID ? "cell_residual" : "cell_jacobi", s);
+    const bool res = op == OP_RESID || op == OP_RESID32;
+    Prof p(h, op == OP_APPLY ? "cell_apply" : res ? "cell_residual" : "cell_jacobi", s);
     launch_cell(dtype, op, J, ca, s);
     check_launch();
   }
   ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
                           m.d_partials + kCellWaves * ca.nblocks, R);
-  if (op == OP_RESID) ea.u = x;
+  if (op == OP_RESID || op == OP_RESID32) ea.u = x;
+  ea.y32 = y32;
   if (ea.total > 0) {
     Prof p(h, "exchange", s);
     launch_exchange(dtype, op, ea, s);
     check_launch();
   }
-  if ((op == OP_RESID || op == OP_JACOBI) && want_norm) {
+  if ((op == OP_RESID || op == OP_RESID32 || op == OP_JACOBI) && want_norm) {
     const int64_t cnt = kCellWaves * ca.nblocks + (ea.total + 255) / 256;
     Prof p(h, "norm_sum", s);
     launch_sum_partials(m.d_partials, cnt, m.d_scalar + scalar_slot, true, s);
@@ -1034,13 +1039,18 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
     const double bnorm = norm_of(h, level, HT_F64, b, b, s, true);
     const double scale = bnorm > 0 ? 1.0 / bnorm : 1.0;
     LevelWork& w64 = work(h, level, HT_F64);
-    // residual of the initial iterate
-    op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, s, true, 0);
+    const bool mixed = o->precision == HT_PREC_MIXED;
+    LevelWork* w32 = mixed ? &work(h, level, HT_F32) : nullptr;
+    // residual of the initial iterate (mixed: delivered in FP32 as the
+    // right-hand side of the first correction)
+    if (mixed)
+      op_pass(h, level, HT_F64, OP_RESID32, u, w64.t, b, 0.0, s, true, 0,
+              full_range(h->m), w32->b);
+    else
+      op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, s, true, 0);
     double rel = read_scalar(h, 0, s) * scale;
     st->res_history[0] = rel;
     int k = 0;
-    const bool mixed = o->precision == HT_PREC_MIXED;
-    LevelWork* w32 = mixed ? &work(h, level, HT_F32) : nullptr;
     // FP64 cycles: the first Jacobi sweep of the next cycle (out of place,
     // u -> t) also yields |b - A u| of the iterate it starts from, so each
     // cycle's graph ends with that sweep instead of a separate residual
@@ -1063,11 +1073,12 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
         vcycle_top(h, level, HT_F64, o->cyc, u, b, false, ss);
         op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, ss, true, 0);
       } else {
-        // FP32 correction of the FP64 residual held in w64.t
-        flat(h, level, HT_F32, HT_F64, FOP_COPY, w32->b, w64.t, ss);
+        // FP32 correction of the FP64 residual (rounded to FP32 in w32->b),
+        // FP64 update, FP64 residual of the new iterate rounded to FP32
         void* e = vcycle_impl(h, level, HT_F32, o->cyc, w32->u, w32->t, w32->b, true, ss);
         flat(h, level, HT_F64, HT_F32, FOP_ADD, u, e, ss);
-        op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, ss, true, 0);
+        op_pass(h, level, HT_F64, OP_RESID32, u, w64.t, b, 0.0, ss, true, 0,
+                full_range(h->m), w32->b);
       }
       HT_CHECK_HIP(hipMemcpyAsync(h->m.h_scalar, h->m.d_scalar, sizeof(double),
                                   hipMemcpyDeviceToHost, ss));

@@ -273,7 +273,10 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
     }
   };
 
-  constexpr bool NEED_B = (OP == OP_RESID || OP == OP_JACOBI);
+  constexpr bool NEED_B = (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32);
+  const __amdgpu_buffer_rsrc_t ry32 = make_rsrc(
+      OP == OP_RESID32 ? (float*)a.y32 + cell * a.stride : (float*)a.y,
+      a.stride * (int64_t)sizeof(float));
   double nsq = 0.0;
   // One plane step: compute plane k from (pm, pc, pp) = planes k-1, k, k+1
   // while the loads of plane k+2 go into pn.  The k loop is unrolled by four
@@ -393,8 +396,15 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
         nsq += counted ? (double)r * (double)r : 0.0;
         if (OP == OP_RESID) {
           out = surf ? acc : r;
-        } else {
+        } else if (OP == OP_JACOBI) {
           out = surf ? acc : fma(omega_invd, r, c);
+        }
+        if (OP == OP_RESID32) {
+          // finished points: FP32 residual (element offset = so / 2);
+          // surface points: the FP64 partial row, completed by the exchange
+          bstore((float)r, ry32, surf ? HT_OOB : so >> 1);
+          bstore(acc, ry, surf ? so : HT_OOB);
+          continue;
         }
       }
       bstore(out, ry, so);
@@ -516,7 +526,7 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       T val;
       if (P.boundary) {
         val = (OP == OP_JACOBI) ? ((const T*)a.u)[s0] : (T)0;
-      } else if (OP == OP_RESID) {
+      } else if (OP == OP_RESID || OP == OP_RESID32) {
         val = ((const T*)a.b)[s0] - sum;
         nsq = (double)val * (double)val;
       } else if (OP == OP_JACOBI) {
@@ -527,11 +537,17 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       } else {
         val = sum;
       }
-      y[s0] = val;
-      for (int q = 1; q < cnt; ++q) y[slot_q(q)] = val;
+      if (OP == OP_RESID32) {
+        float* y32 = (float*)a.y32;
+        y32[s0] = (float)val;
+        for (int q = 1; q < cnt; ++q) y32[slot_q(q)] = (float)val;
+      } else {
+        y[s0] = val;
+        for (int q = 1; q < cnt; ++q) y[slot_q(q)] = val;
+      }
     }
   }
-  if (OP == OP_RESID || OP == OP_JACOBI) {
+  if (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32) {
     __shared__ double red[4];
     nsq = wave_sum(nsq);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nsq;
@@ -882,8 +898,10 @@ void launch_cell(int dtype, int op, int J, const CellArgs& a, hipStream_t s) {
     if (op == OP_APPLY) launch_cell_t<double, OP_APPLY>(a, J, s);
     else if (op == OP_RESID) launch_cell_t<double, OP_RESID>(a, J, s);
     else if (op == OP_JACOBI) launch_cell_t<double, OP_JACOBI>(a, J, s);
+    else if (op == OP_RESID32) launch_cell_t<double, OP_RESID32>(a, J, s);
     else launch_cell_t<double, OP_RESTRICT>(a, J, s);
   } else {
+    if (op == OP_RESID32) throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input"};
     if (op == OP_APPLY) launch_cell_t<float, OP_APPLY>(a, J, s);
     else if (op == OP_RESID) launch_cell_t<float, OP_RESID>(a, J, s);
     else if (op == OP_JACOBI) launch_cell_t<float, OP_JACOBI>(a, J, s);
@@ -901,16 +919,19 @@ static void launch_exchange_t(int op, const ExchArgs& a, hipStream_t s) {
     case OP_SYNC: hipLaunchKernelGGL((k_exchange<T, OP_SYNC>), grid, dim3(256), 0, s, a); break;
     case OP_FILL: hipLaunchKernelGGL((k_exchange<T, OP_FILL>), grid, dim3(256), 0, s, a); break;
     case OP_RESTRICT: hipLaunchKernelGGL((k_exchange<T, OP_RESTRICT>), grid, dim3(256), 0, s, a); break;
+    case OP_RESID32: hipLaunchKernelGGL((k_exchange<T, OP_RESID32>), grid, dim3(256), 0, s, a); break;
   }
 }
 void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
   if (a.total <= 0) return;
   if (op != OP_APPLY && op != OP_RESID && op != OP_JACOBI && op != OP_SYNC &&
-      op != OP_FILL && op != OP_RESTRICT)
+      op != OP_FILL && op != OP_RESTRICT && op != OP_RESID32)
     throw Error{HT_ERR_ARG, "unknown exchange operation"};
   // the residual and Jacobi epilogues read u and b at the owner copy
-  if ((op == OP_RESID || op == OP_JACOBI) && (!a.u || !a.b))
+  if ((op == OP_RESID || op == OP_JACOBI || op == OP_RESID32) && (!a.u || !a.b))
     throw Error{HT_ERR_ARG, "exchange for residual/Jacobi needs u and b"};
+  if (op == OP_RESID32 && (dtype != HT_F64 || !a.y32))
+    throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input and y32"};
   if (dtype == HT_F64) launch_exchange_t<double>(op, a, s);
   else launch_exchange_t<float>(op, a, s);
 }

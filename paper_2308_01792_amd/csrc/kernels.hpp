@@ -7,8 +7,12 @@
 
 namespace ht {
 
+// OP_RESID32: FP64 residual delivered in FP32 (iterative refinement): the
+// cell kernel writes finished points straight to y32 and FP64 partial rows
+// of surface points to y; the exchange completes those in FP64 and writes
+// y32.
 enum { OP_APPLY = 0, OP_RESID = 1, OP_JACOBI = 2, OP_SYNC = 3, OP_FILL = 4,
-       OP_RESTRICT = 5 };
+       OP_RESTRICT = 5, OP_RESID32 = 6 };
 enum { EOP_ZERO_GUESS = 0, EOP_MASS = 1, EOP_ZERO_INTERIOR = 2, EOP_DOT = 3,
        EOP_FLAGS = 4, EOP_COORDS = 5 };
 enum { FOP_COPY = 0, FOP_ADD = 1, FOP_ZERO = 2 };
@@ -23,6 +27,7 @@ enum { kCellWaves = HT_CELL_WAVES };
 struct CellArgs {
   const void* x;        // operand (u for residual / Jacobi)
   void* y;              // output
+  void* y32;            // FP32 residual (OP_RESID32)
   const void* b;        // right-hand side (residual / Jacobi)
   const void* w;        // level-scaled class stencils [nc][16][15]
   const ClassInfo* cls; // [nc][16]
@@ -38,6 +43,7 @@ struct CellArgs {
 
 struct ExchArgs {
   void* y;
+  void* y32;            // FP32 residual (OP_RESID32)
   const void* u;
   const void* b;
   const DevPrim* prim;

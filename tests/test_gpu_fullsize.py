@@ -309,3 +309,38 @@ def test_solve_both_precisions_at_full_size(big):
     assert diff <= 1e-8
     del b, u64, u32
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_unit_cube_discrete_solution_closed_form(precision):
+    """Unit cube as 6 Kuhn tets at level 7 (2,048,383 unknowns): with the
+    lumped right-hand side of f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) the
+    P1 system is the 7-point scheme, whose solution is c_h u(x) at every
+    node, c_h = (pi h / 2)^2 / sin^2(pi h / 2).  Checks the whole GPU solve
+    against this closed form, without the oracle."""
+    from workloads import kuhn_box
+    L = 7
+    m = ht.Mesh(*kuhn_box(1, 1, 1), 2, L)
+    ns = m.n_slots(L)
+    X = torch.zeros(3 * ns, dtype=torch.float64, device="cuda")
+    m.coords_device(L, X)
+    X = X.view(-1, 3)
+    s = (torch.sin(np.pi * X[:, 0]) * torch.sin(np.pi * X[:, 1]) *
+         torch.sin(np.pi * X[:, 2]))
+    mass = torch.zeros(ns, dtype=torch.float64, device="cuda")
+    m.lumped_mass(L, mass)
+    b = mass * (3 * np.pi ** 2) * s
+    u = torch.zeros_like(b)
+    prec = ht.HT_PREC_F64 if precision == "f64" else ht.HT_PREC_MIXED
+    st = m.solve(L, u, b, prec, 1e-11, 100)
+    assert st["converged"]
+    h = 2.0 ** -L
+    ch = (np.pi * h / 2) ** 2 / np.sin(np.pi * h / 2) ** 2
+    f = torch.zeros(ns, dtype=torch.uint8, device="cuda")
+    m.flags_device(L, f)
+    interior = ((f & ht.HT_SLOT_DIRICHLET) == 0) & ((f & ht.HT_SLOT_PAD) == 0)
+    err = (u - ch * s)[interior].abs().max().item()
+    assert err <= 1e-8, err        # discretisation error: 5e-5
+    # and it is not the continuous solution: the discretisation error shows
+    assert (u - s)[interior].abs().max().item() > 1e-5
+    m.close()
