@@ -239,6 +239,19 @@ int ht_batch_solve(ht_batch* batch, const ht_solve_opts* opts,
                    void* const* u, const void* const* b, ht_solve_stats* stats,
                    ht_stream stream);
 
+/* Full multigrid (nested iteration) for A u = b at `level` with zero
+ * Dirichlet data.  A function lives on every level (Section 5.1), so the
+ * right-hand side is carried down by the restriction (b_{l-1} = R b_l),
+ * the system at opts->coarse_level is solved exactly, and on each finer
+ * level the interpolated coarser solution (P u_{l-1}) starts `cycles`
+ * V(nu1, nu2) cycles.  u: HT_F64 output at `level` (overwritten;
+ * Dirichlet slots set to 0); b: HT_F64 right-hand side.  rel_res (may be
+ * NULL): ||b - A u||_2 / ||b||_2 of the result, which synchronises.  The
+ * whole sequence is captured once per (level, opts, cycles, u, b) as a
+ * hipGraph and replayed.  HT_ERR_ARG for cycles outside [1, 64]. */
+int ht_fmg(ht_mesh* mesh, int level, const ht_cycle_opts* opts, int cycles,
+           void* u, const void* b, double* rel_res, ht_stream stream);
+
 /* ------------------------------------------------------------- tuning -- */
 /* The stencil kernel runs one wavefront per tile of 64 i-points x R rows,
  * marching in k.  R in {4, 8, 16} trades register pressure against halo

@@ -126,6 +126,29 @@ class Hierarchy:
         u = self.prolongate_add(lvl - 1, ec, u)
         return S.jacobi(u, b, omega, nu2)
 
+    def fmg(self, lvl: int, b: np.ndarray, cycles: int = 1, nu1: int = 2,
+            nu2: int = 2, omega: float = 2.0 / 3.0,
+            coarse_level: int | None = None) -> np.ndarray:
+        """Full multigrid (nested iteration) for A u = b on level lvl with
+        zero Dirichlet data: the right-hand side is carried down by the
+        restriction (b_{l-1} = R b_l), the coarsest system is solved
+        exactly, and on every finer level the interpolated coarser solution
+        (P u_{l-1}) starts `cycles` V(nu1, nu2) cycles."""
+        if coarse_level is None:
+            coarse_level = self.min_level
+        rhs = {lvl: b}
+        for lv in range(lvl, coarse_level, -1):
+            rhs[lv - 1] = self.restrict(lv, rhs[lv])
+        u = self.coarse_solve(coarse_level,
+                              np.zeros(self.sys[coarse_level].mesh.num_vertices),
+                              rhs[coarse_level])
+        for lv in range(coarse_level + 1, lvl + 1):
+            u = self.prolongate_add(lv - 1, u,
+                                    np.zeros(self.sys[lv].mesh.num_vertices))
+            for _ in range(cycles):
+                u = self.vcycle(lv, u, rhs[lv], nu1, nu2, omega, coarse_level)
+        return u
+
     def solve(self, lvl: int, b: np.ndarray, u0: np.ndarray | None = None,
               rel_tol: float = 1e-10, max_cycles: int = 50, nu1: int = 2,
               nu2: int = 2, omega: float = 2.0 / 3.0,

@@ -226,6 +226,16 @@ class Mesh:
                 "rel_res": st.rel_res, "seconds": st.seconds,
                 "history": list(st.res_history[:st.cycles + 1])}
 
+    def fmg(self, level: int, u, b, cycles=5, nu1=2, nu2=2, omega=2.0 / 3.0,
+            coarse_level=2, want_residual=True):
+        """Full multigrid into u; returns the relative residual (or None)."""
+        o = self.cycle_opts(nu1, nu2, omega, coarse_level)
+        r = C.c_double()
+        check(load().ht_fmg(self._h, level, C.byref(o), int(cycles), _ptr(u),
+                            _ptr(b), C.byref(r) if want_residual else None,
+                            _stream()))
+        return r.value if want_residual else None
+
     # -------------------------------------------------------- tuning ----
     def set_tile_rows(self, level: int, dtype_code: int, rows: int):
         check(load().ht_set_tile_rows(self._h, level, dtype_code, rows))

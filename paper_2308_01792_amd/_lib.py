@@ -74,6 +74,7 @@ SIGNATURES = {
     "ht_vcycle": (I, [P, I, I, C.POINTER(CycleOpts), P, P, P]),
     "ht_solve": (I, [P, I, C.POINTER(SolveOpts), P, P,
                      C.POINTER(SolveStats), P]),
+    "ht_fmg": (I, [P, I, C.POINTER(CycleOpts), I, P, P, C.POINTER(D), P]),
     "ht_batch_create": (I, [C.POINTER(P), C.POINTER(I), I, C.POINTER(P)]),
     "ht_batch_destroy": (I, [P]),
     "ht_batch_query": (I, [P, C.POINTER(I), C.POINTER(L), C.POINTER(L)]),

@@ -1116,6 +1116,57 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
   return rc;
 }
 
+int ht_fmg(ht_mesh* h, int level, const ht_cycle_opts* o, int cycles, void* u,
+           const void* b, double* rel_res, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, HT_F64);
+    check_cycle(h->m, level, o);
+    check_ptr(u, "u");
+    check_ptr(b, "b");
+    if (cycles < 1 || cycles > 64) throw Error{HT_ERR_ARG, "cycles must be in [1, 64]"};
+    const int lc = o->coarse_level;
+    // set-up before capture: workspace and the coarse solver
+    coarse_solver(h, lc);
+    for (int l = lc; l <= level; ++l) work(h, l, HT_F64);
+    auto body = [&](hipStream_t ss) {
+      const Range R = full_range(h->m);
+      // right-hand sides of the coarser levels: b_{l-1} = R b_l
+      const void* bl = b;
+      for (int l = level; l > lc; --l) {
+        restrict_pass(h, l, HT_F64, bl, work(h, l - 1, HT_F64).b, ss, R);
+        bl = work(h, l - 1, HT_F64).b;
+      }
+      if (level == lc) {
+        flat(h, lc, HT_F64, HT_F64, FOP_ZERO, u, nullptr, ss);
+        coarse_fast(h, lc, HT_F64, b, u, ss);
+        return;
+      }
+      LevelWork& w0 = work(h, lc, HT_F64);
+      flat(h, lc, HT_F64, HT_F64, FOP_ZERO, w0.u, nullptr, ss);
+      coarse_fast(h, lc, HT_F64, w0.b, w0.u, ss);
+      // upwards: interpolate, then V-cycles on each level
+      for (int l = lc + 1; l <= level; ++l) {
+        LevelWork& wl = work(h, l, HT_F64);
+        void* ul = l == level ? u : wl.u;
+        const void* rl = l == level ? b : wl.b;
+        flat(h, l, HT_F64, HT_F64, FOP_ZERO, ul, nullptr, ss);
+        prolong_pass(h, l - 1, HT_F64, work(h, l - 1, HT_F64).u, ul, ss, R);
+        for (int c = 0; c < cycles; ++c) vcycle_top(h, l, HT_F64, *o, ul, rl, false, ss);
+      }
+    };
+    std::ostringstream key;
+    key << "fmg:" << level << ':' << o->nu1 << ':' << o->nu2 << ':' << o->omega << ':'
+        << lc << ':' << cycles << ':' << u << ':' << b;
+    run_graph(h, key.str(), body, s);
+    if (rel_res) {
+      const double bn = norm_of(h, level, HT_F64, b, b, s, true);
+      op_pass(h, level, HT_F64, OP_RESID, u, work(h, level, HT_F64).t, b, 0.0, s, true, 0);
+      const double rn = read_scalar(h, 0, s);
+      *rel_res = bn > 0 ? rn / bn : rn;
+    }
+  });
+}
+
 int ht_batch_create(ht_mesh* const* meshes, const int* levels, int n,
                     ht_batch** out) {
   return guard([&] {

@@ -344,3 +344,34 @@ def test_unit_cube_discrete_solution_closed_form(precision):
     # and it is not the continuous solution: the discretisation error shows
     assert (u - s)[interior].abs().max().item() > 1e-5
     m.close()
+
+
+def test_fmg_unit_cube_reaches_discretisation_error():
+    """Full multigrid with five V(2,2) per level on the unit cube at level 7:
+    the algebraic error against the exact discrete solution c_h u is well
+    below the discretisation error (c_h - 1) max |u|, with no iteration to a
+    residual tolerance."""
+    from workloads import kuhn_box
+    L = 7
+    m = ht.Mesh(*kuhn_box(1, 1, 1), 2, L)
+    ns = m.n_slots(L)
+    X = torch.zeros(3 * ns, dtype=torch.float64, device="cuda")
+    m.coords_device(L, X)
+    X = X.view(-1, 3)
+    s = (torch.sin(np.pi * X[:, 0]) * torch.sin(np.pi * X[:, 1]) *
+         torch.sin(np.pi * X[:, 2]))
+    mass = torch.zeros(ns, dtype=torch.float64, device="cuda")
+    m.lumped_mass(L, mass)
+    b = mass * (3 * np.pi ** 2) * s
+    m.fill_dirichlet(L, b, 0.0)
+    u = torch.zeros_like(b)
+    m.fmg(L, u, b, cycles=5)
+    h = 2.0 ** -L
+    ch = (np.pi * h / 2) ** 2 / np.sin(np.pi * h / 2) ** 2
+    f = torch.zeros(ns, dtype=torch.uint8, device="cuda")
+    m.flags_device(L, f)
+    interior = ((f & ht.HT_SLOT_DIRICHLET) == 0) & ((f & ht.HT_SLOT_PAD) == 0)
+    disc = (ch - 1.0) * s[interior].abs().max().item()
+    err = (u - ch * s)[interior].abs().max().item()
+    assert err <= 0.25 * disc, (err, disc)
+    m.close()

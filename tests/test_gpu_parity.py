@@ -325,3 +325,21 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     P.m.set_tile_rows(4, ht.HT_F64, 4 if rows != 4 else 8)
     assert P.m.autotune(4, ht.HT_F64, cache) == rows      # from the cache
     assert open(cache).read().count("\n") == 1
+
+
+@pytest.mark.parametrize("cycles", [1, 3])
+def test_fmg_matches_oracle(cycles):
+    """Full multigrid (restricted right-hand sides, exact coarse solve,
+    interpolation, V(2,2) per level) against the oracle's nested
+    iteration."""
+    P = pair("jittered_288", 4, 2)
+    S = P.S(4)
+    b = np.where(S.dirichlet, 0.0,
+                 S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5))
+    bg = P.to_gpu(4, b)
+    ug = torch.full_like(bg, np.nan)
+    rel = P.m.fmg(4, ug, bg, cycles=cycles)
+    uo = P.H.fmg(4, b, cycles=cycles, coarse_level=2)
+    assert rel_err(P.from_gpu(4, ug), uo) <= 1e-11
+    ro = np.linalg.norm(S.residual(uo, b)) / np.linalg.norm(b[S.interior])
+    assert rel == pytest.approx(ro, rel=1e-6)

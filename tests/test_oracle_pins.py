@@ -415,6 +415,49 @@ def test_c2_second_order_convergence():
     assert ((ratios > 3.8) & (ratios < 4.2)).all(), ratios
 
 
+# ------------------------------------------------ full multigrid (FMG) --
+def _c2_problem(H, lvl):
+    """Lumped sine right-hand side on the unit cube and its exact discrete
+    solution c_h u(x) (the 7-point scheme's eigenfunction)."""
+    S = H[lvl]
+    b = np.where(S.dirichlet, 0.0,
+                 S.lumped_mass * fields.sine_source(S.mesh.xyz))
+    h = 1.0 / S.mesh.n
+    ch = (np.pi * h / 2) ** 2 / np.sin(np.pi * h / 2) ** 2
+    u = fields.sine_solution(S.mesh.xyz)
+    disc = np.abs((ch - 1.0) * u)[S.interior].max()
+    return S, b, ch * u, disc
+
+
+def test_fmg_converges_to_the_discrete_solution():
+    """Many cycles per level: nested iteration ends at the exact discrete
+    solution, known in closed form."""
+    H = oracle_hierarchy("kuhn_cube", 4, 2)
+    S, b, uh, disc = _c2_problem(H, 4)
+    u = H.fmg(4, b, cycles=30, coarse_level=2)
+    assert np.abs(u - uh)[S.interior].max() <= 1e-9 * disc
+
+
+def test_fmg_reaches_the_discretisation_error():
+    """Five V(2,2) per level leave an algebraic error well below the
+    discretisation error, on every level (the defining property of nested
+    iteration: the error does not accumulate across levels)."""
+    H = oracle_hierarchy("kuhn_cube", 5, 2)
+    for lvl in (3, 4, 5):
+        S, b, uh, disc = _c2_problem(H, lvl)
+        u = H.fmg(lvl, b, cycles=5, coarse_level=2)
+        assert np.abs(u - uh)[S.interior].max() <= 0.25 * disc
+
+
+def test_fmg_on_the_coarse_level_is_the_direct_solve():
+    H = oracle_hierarchy("jittered_288", 2, 2)
+    S = H[2]
+    b = np.where(S.dirichlet, 0.0, fields.uniform_values(S.mesh.num_vertices, 8))
+    u = H.fmg(2, b, cycles=1, coarse_level=2)
+    AII, I = S.interior_matrix()
+    assert np.allclose(u[I], spla.spsolve(AII.tocsc(), b[I]), rtol=1e-12, atol=1e-14)
+
+
 # ----------------------------------- second, lattice-based oracle for C1 --
 def test_c1_lattice_stencil_reproduces_oracle():
     """A separate lattice code (closed-form stencil on the index grid of the
