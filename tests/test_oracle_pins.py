@@ -458,6 +458,75 @@ def test_fmg_on_the_coarse_level_is_the_direct_solve():
     assert np.allclose(u[I], spla.spsolve(AII.tocsc(), b[I]), rtol=1e-12, atol=1e-14)
 
 
+# ------------------------------------------------- Chebyshev smoother --
+def _generalised_eigen(S):
+    """Eigenpairs of D^-1 A on the interior unknowns (A v = lam D v)."""
+    import scipy.linalg as sla
+    AII, I = S.interior_matrix()
+    A = AII.toarray()
+    lam, V = sla.eigh(A, np.diag(np.diag(A)))
+    return lam, V, I
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_chebyshev_smoother_is_the_chebyshev_polynomial(degree):
+    """With b = 0 the smoother maps an eigenvector of D^-1 A (eigenvalue lam)
+    to T_m((beta+alpha-2 lam)/(beta-alpha)) / T_m((beta+alpha)/(beta-alpha))
+    times itself."""
+    from numpy.polynomial import chebyshev as cheb
+    from oracle.mg import chebyshev_smooth
+    S = oracle_hierarchy("jittered_222", 2, 2)[2]
+    lam, V, I = _generalised_eigen(S)
+    alpha, beta = 0.07, 2.0
+    Tm = [0] * degree + [1]
+    for idx in (0, 40, len(lam) // 2, len(lam) - 1):
+        u = np.zeros(S.mesh.num_vertices)
+        u[I] = V[:, idx]
+        out = chebyshev_smooth(S, u, np.zeros_like(u), degree, alpha, beta)
+        p = (cheb.chebval((beta + alpha - 2 * lam[idx]) / (beta - alpha), Tm) /
+             cheb.chebval((beta + alpha) / (beta - alpha), Tm))
+        assert np.abs(out[I] - p * V[:, idx]).max() <= 1e-13
+
+
+def test_chebyshev_degree_one_is_jacobi():
+    """Degree 1 is a Jacobi sweep with weight 1/theta."""
+    from oracle.mg import chebyshev_smooth
+    S = oracle_hierarchy("jittered_222", 3, 2)[3]
+    u = np.where(S.dirichlet, 0.0, fields.uniform_values(S.mesh.num_vertices, 1))
+    b = fields.uniform_values(S.mesh.num_vertices, 2)
+    alpha, beta = 0.05, 2.1
+    out = chebyshev_smooth(S, u, b, 1, alpha, beta)
+    assert np.allclose(out, S.jacobi(u, b, 2.0 / (alpha + beta)), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("level", [2, 3])
+def test_power_iteration_brackets_the_largest_eigenvalue(level):
+    """The estimate is below the largest eigenvalue of D^-1 A and the upper
+    end of the smoothing interval (1.1 times it) is above."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    from oracle.mg import CHEB_UPPER, lambda_max_estimate
+    S = oracle_hierarchy("jittered_222", 3, 2)[level]
+    AII, _ = S.interior_matrix()
+    lmax = sla.eigsh(AII, k=1, M=sp.diags(AII.diagonal()), which="LA")[0][0]
+    est = lambda_max_estimate(S)
+    assert est <= lmax * (1 + 1e-12) and CHEB_UPPER * est >= lmax
+
+
+def test_vcycle_with_chebyshev_smoother_converges():
+    H = oracle_hierarchy("jittered_222", 3, 2)
+    S = H[3]
+    b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 4)
+    u = np.zeros_like(b)
+    hist = [np.linalg.norm(S.residual(u, b))]
+    for _ in range(12):
+        u = H.vcycle(3, u, b, 1, 1, coarse_level=2, smoother="chebyshev",
+                     degree=2)
+        hist.append(np.linalg.norm(S.residual(u, b)))
+    rates = np.array(hist[1:]) / np.array(hist[:-1])
+    assert rates.max() < 0.35 and hist[-1] <= 1e-7 * hist[0]
+
+
 # ----------------------------------- second, lattice-based oracle for C1 --
 def test_c1_lattice_stencil_reproduces_oracle():
     """A separate lattice code (closed-form stencil on the index grid of the
