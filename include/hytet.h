@@ -68,6 +68,7 @@ enum {
 };
 enum { HT_F64 = 0, HT_F32 = 1 };
 enum { HT_PREC_F64 = 0, HT_PREC_MIXED = 1 };
+enum { HT_SMOOTH_JACOBI = 0, HT_SMOOTH_CHEBYSHEV = 1 };
 enum {
   HT_SLOT_OWNER = 1,     /* the owning copy of its micro-vertex */
   HT_SLOT_GHOST = 2,     /* a further copy of a shared micro-vertex */
@@ -84,9 +85,12 @@ typedef struct {
 } ht_level_info;
 
 typedef struct {
-  int nu1, nu2;        /* pre- and post-smoothing sweeps */
+  int nu1, nu2;        /* pre- and post-smoother applications */
   double omega;        /* Jacobi weight, e.g. 2/3 */
   int coarse_level;    /* level solved exactly (dense Cholesky inverse) */
+  int smoother;        /* HT_SMOOTH_JACOBI (0) or HT_SMOOTH_CHEBYSHEV */
+  int degree;          /* Chebyshev: polynomial degree (stencil passes per
+                          application), 1..16; ignored for Jacobi */
 } ht_cycle_opts;
 
 typedef struct {
@@ -238,6 +242,18 @@ int ht_batch_query(const ht_batch* batch, int* n_problems, int64_t* n_dofs,
 int ht_batch_solve(ht_batch* batch, const ht_solve_opts* opts,
                    void* const* u, const void* const* b, ht_solve_stats* stats,
                    ht_stream stream);
+
+/* Smoothers.  HT_SMOOTH_JACOBI: omega-weighted Jacobi sweeps.
+ * HT_SMOOTH_CHEBYSHEV: the Chebyshev iteration of the given degree for the
+ * Jacobi-preconditioned system D^-1 A u = D^-1 b on [beta/8, beta] (the
+ * paper's large runs accelerate Jacobi with Chebyshev polynomials, Sections
+ * 5.2.1 and 6), beta = 1.1 times the estimate of ht_lambda_max.  The
+ * estimates are computed once per level on first use (before any graph
+ * capture).  ht_lambda_max: 20 power iterations v <- D^-1 A v from
+ * v = sin(1000 x + 1700 y + 2300 z) (zero on the boundary); the estimate is
+ * |v_20| / |v_19| over the unique non-Dirichlet micro-vertices.  Allocates
+ * two scratch vectors; synchronises. */
+int ht_lambda_max(ht_mesh* mesh, int level, double* lambda, ht_stream stream);
 
 /* Full multigrid (nested iteration) for A u = b at `level` with zero
  * Dirichlet data.  A function lives on every level (Section 5.1), so the

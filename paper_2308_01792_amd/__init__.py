@@ -13,11 +13,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import (HT_F32, HT_F64, HT_PREC_F64, HT_PREC_MIXED,
+                   HT_SMOOTH_CHEBYSHEV, HT_SMOOTH_JACOBI,
                    HT_SLOT_DIRICHLET, HT_SLOT_GHOST, HT_SLOT_OWNER,
                    HT_SLOT_PAD, HytetError, check)
 
 __all__ = ["Mesh", "Batch", "HytetError", "load", "HT_F64", "HT_F32", "HT_PREC_F64",
-           "HT_PREC_MIXED", "HT_SLOT_OWNER", "HT_SLOT_GHOST",
+           "HT_PREC_MIXED", "HT_SMOOTH_JACOBI", "HT_SMOOTH_CHEBYSHEV",
+           "HT_SLOT_OWNER", "HT_SLOT_GHOST",
            "HT_SLOT_DIRICHLET", "HT_SLOT_PAD", "index_tw",
            "selftest_lane_shift"]
 
@@ -202,20 +204,28 @@ class Mesh:
         return u
 
     @staticmethod
-    def cycle_opts(nu1=2, nu2=2, omega=2.0 / 3.0, coarse_level=2):
-        return _lib.CycleOpts(nu1, nu2, omega, coarse_level)
+    def cycle_opts(nu1=2, nu2=2, omega=2.0 / 3.0, coarse_level=2,
+                   smoother=HT_SMOOTH_JACOBI, degree=2):
+        return _lib.CycleOpts(nu1, nu2, omega, coarse_level, smoother, degree)
+
+    def lambda_max(self, level: int) -> float:
+        r = C.c_double()
+        check(load().ht_lambda_max(self._h, level, C.byref(r), _stream()))
+        return r.value
 
     def vcycle(self, level: int, u, b, nu1=2, nu2=2, omega=2.0 / 3.0,
-               coarse_level=2):
-        o = self.cycle_opts(nu1, nu2, omega, coarse_level)
+               coarse_level=2, smoother=HT_SMOOTH_JACOBI, degree=2):
+        o = self.cycle_opts(nu1, nu2, omega, coarse_level, smoother, degree)
         check(load().ht_vcycle(self._h, level, _dtype_code(u), C.byref(o),
                                _ptr(u), _ptr(b), _stream()))
         return u
 
     def solve(self, level: int, u, b, precision=HT_PREC_F64, rel_tol=1e-10,
               max_cycles=100, nu1=2, nu2=2, omega=2.0 / 3.0, coarse_level=2,
-              use_graph=True, raise_on_fail=True):
-        o = _lib.SolveOpts(self.cycle_opts(nu1, nu2, omega, coarse_level),
+              use_graph=True, raise_on_fail=True, smoother=HT_SMOOTH_JACOBI,
+              degree=2):
+        o = _lib.SolveOpts(self.cycle_opts(nu1, nu2, omega, coarse_level,
+                                           smoother, degree),
                            precision, rel_tol, max_cycles, int(use_graph))
         st = _lib.SolveStats()
         code = load().ht_solve(self._h, level, C.byref(o), _ptr(u), _ptr(b),
@@ -227,9 +237,10 @@ class Mesh:
                 "history": list(st.res_history[:st.cycles + 1])}
 
     def fmg(self, level: int, u, b, cycles=5, nu1=2, nu2=2, omega=2.0 / 3.0,
-            coarse_level=2, want_residual=True):
+            coarse_level=2, want_residual=True, smoother=HT_SMOOTH_JACOBI,
+            degree=2):
         """Full multigrid into u; returns the relative residual (or None)."""
-        o = self.cycle_opts(nu1, nu2, omega, coarse_level)
+        o = self.cycle_opts(nu1, nu2, omega, coarse_level, smoother, degree)
         r = C.c_double()
         check(load().ht_fmg(self._h, level, C.byref(o), int(cycles), _ptr(u),
                             _ptr(b), C.byref(r) if want_residual else None,

@@ -27,9 +27,13 @@ class LevelInfo(C.Structure):
                 ("n_vertices", C.c_int64), ("cell_stride", C.c_int64)]
 
 
+HT_SMOOTH_JACOBI, HT_SMOOTH_CHEBYSHEV = 0, 1
+
+
 class CycleOpts(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("omega", C.c_double),
-                ("coarse_level", C.c_int)]
+                ("coarse_level", C.c_int), ("smoother", C.c_int),
+                ("degree", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -75,6 +79,7 @@ SIGNATURES = {
     "ht_solve": (I, [P, I, C.POINTER(SolveOpts), P, P,
                      C.POINTER(SolveStats), P]),
     "ht_fmg": (I, [P, I, C.POINTER(CycleOpts), I, P, P, C.POINTER(D), P]),
+    "ht_lambda_max": (I, [P, I, C.POINTER(D), P]),
     "ht_batch_create": (I, [C.POINTER(P), C.POINTER(I), I, C.POINTER(P)]),
     "ht_batch_destroy": (I, [P]),
     "ht_batch_query": (I, [P, C.POINTER(I), C.POINTER(L), C.POINTER(L)]),

@@ -42,6 +42,7 @@ struct ht_mesh {
   // level -> walk tiles (64 i x 8 rows) for the transfer / elementwise kernels
   std::map<int, std::pair<int2*, int64_t>> walk_tiles;
   std::map<std::pair<int, int>, int> tuned_J;  // (level, dtype) -> J
+  std::map<int, double> lambda_max;            // level -> estimate
   bool capturing = false;
 };
 
@@ -517,6 +518,12 @@ static void* sweeps(ht_mesh* h, int level, int dtype, double omega, int count,
   return cur;
 }
 
+static void* smooth(ht_mesh* h, int level, int dtype, const ht_cycle_opts& o,
+                    int count, void* cur, void* other, const void* b,
+                    hipStream_t s);
+static double norm_of(ht_mesh* h, int level, int dtype, const void* a,
+                      const void* b, hipStream_t s, bool sq);
+
 // V(nu1, nu2) on `level`: iterate in u (or t), returns the buffer with the
 // new iterate.  zero_guess: the incoming iterate is zero.  first_done: the
 // first pre-smoothing sweep has already been made from u into t.
@@ -532,21 +539,21 @@ static void* vcycle_impl(ht_mesh* h, int level, int dtype,
   void* other = first_done ? u : t;
   int todo = first_done ? o.nu1 - 1 : o.nu1;
   if (zero_guess) {
-    if (todo > 0) {
+    if (todo > 0 && o.smoother == HT_SMOOTH_JACOBI) {
       zero_guess_sweep(h, level, dtype, o.omega, cur, b, s, full_range(h->m));
       --todo;
     } else {
       flat(h, level, dtype, dtype, FOP_ZERO, cur, nullptr, s);
     }
   }
-  cur = sweeps(h, level, dtype, o.omega, todo, cur, other, b, s);
+  cur = smooth(h, level, dtype, o, todo, cur, other, b, s);
   other = (cur == u) ? t : u;
   op_pass(h, level, dtype, OP_RESID, cur, other, b, 0.0, s);
   LevelWork& wc = work(h, level - 1, dtype);
   restrict_pass(h, level, dtype, other, wc.b, s, full_range(h->m));
   void* ec = vcycle_impl(h, level - 1, dtype, o, wc.u, wc.t, wc.b, true, s);
   prolong_pass(h, level - 1, dtype, ec, cur, s, full_range(h->m));
-  return sweeps(h, level, dtype, o.omega, o.nu2, cur, other, b, s);
+  return smooth(h, level, dtype, o, o.nu2, cur, other, b, s);
 }
 
 static void check_cycle(const Mesh& m, int level, const ht_cycle_opts* o) {
@@ -555,8 +562,125 @@ static void check_cycle(const Mesh& m, int level, const ht_cycle_opts* o) {
     throw Error{HT_ERR_LEVEL, "coarse_level outside [min_level, level]"};
   if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 > 64)
     throw Error{HT_ERR_ARG, "sweep counts must be in [0, 64]"};
-  if (!(o->omega > 0.0 && o->omega < 2.0))
+  if (o->smoother != HT_SMOOTH_JACOBI && o->smoother != HT_SMOOTH_CHEBYSHEV)
+    throw Error{HT_ERR_ARG, "unknown smoother"};
+  if (o->smoother == HT_SMOOTH_JACOBI && !(o->omega > 0.0 && o->omega < 2.0))
     throw Error{HT_ERR_ARG, "omega must lie in (0, 2)"};
+  if (o->smoother == HT_SMOOTH_CHEBYSHEV && (o->degree < 1 || o->degree > 16))
+    throw Error{HT_ERR_ARG, "Chebyshev degree must be in [1, 16]"};
+}
+
+// ----------------------------------------------------- Chebyshev smoother
+// Largest eigenvalue of D^-1 A by power iteration (estimate cached per
+// level).  Runs eagerly with two scratch vectors: call it before capture.
+static double lambda_max_of(ht_mesh* h, int level, hipStream_t s) {
+  auto it = h->lambda_max.find(level);
+  if (it != h->lambda_max.end()) return it->second;
+  Mesh& m = h->m;
+  const size_t bytes = level_slots(m, level) * sizeof(double);
+  double* v = dalloc<double>(level_slots(m, level));
+  double* w = dalloc<double>(level_slots(m, level));
+  double lam = 0.0;
+  try {
+    ElemArgs a = elem_args(h, level);
+    a.out = v;
+    a.alpha = std::ldexp(1.0, -level);
+    launch_elem(HT_F64, EOP_PROBE, a, s);
+    check_launch();
+    double vn = norm_of(h, level, HT_F64, v, v, s, true);
+    for (int it2 = 0; it2 < 20; ++it2) {
+      op_pass(h, level, HT_F64, OP_APPLY, v, w, nullptr, 0.0, s);
+      // w <- D^-1 w (the zero-guess sweep with weight 1), in place
+      ElemArgs z = elem_args(h, level);
+      z.out = w;
+      z.in0 = w;
+      z.alpha = 1.0;
+      launch_elem(HT_F64, EOP_ZERO_GUESS, z, s);
+      check_launch();
+      const double wn = norm_of(h, level, HT_F64, w, w, s, true);
+      lam = vn > 0 ? wn / vn : 0.0;
+      vn = wn;
+      std::swap(v, w);
+    }
+  } catch (...) {
+    (void)hipFree(v);
+    (void)hipFree(w);
+    throw;
+  }
+  HT_CHECK_HIP(hipStreamSynchronize(s));
+  (void)hipFree(v);
+  (void)hipFree(w);
+  (void)bytes;
+  h->lambda_max[level] = lam;
+  return lam;
+}
+
+// Everything the smoother needs on levels (coarse, level]: eigenvalue
+// estimates and direction vectors.  Before any capture.
+static void prepare_smoother(ht_mesh* h, int level, int dtype,
+                             const ht_cycle_opts& o, hipStream_t s) {
+  if (o.smoother != HT_SMOOTH_CHEBYSHEV) return;
+  for (int l = o.coarse_level + 1; l <= level; ++l) {
+    lambda_max_of(h, l, s);
+    LevelWork& w = work(h, l, dtype);
+    if (!w.d) w.d = dalloc<char>(level_slots(h->m, l) * esize(dtype));
+  }
+}
+
+// One Chebyshev step (cell kernel + exchange): d <- c1 d + c2 D^-1 (b - A x),
+// y = x + d.
+static void cheb_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
+                      const void* b, void* d, double c1, double c2,
+                      hipStream_t s) {
+  Mesh& m = h->m;
+  const Range R = full_range(m);
+  const int J = choose_J(h, level, dtype);
+  CellArgs ca = cell_args(h, level, dtype, J, x, y, b, 1.0, R);
+  ca.d = at_cell(d, R.c0, level, dtype);
+  ca.c1 = c1;
+  ca.c2 = c2;
+  {
+    Prof p(h, "cell_chebyshev", s);
+    launch_cell(dtype, OP_CHEB, J, ca, s);
+    check_launch();
+  }
+  ExchArgs ea = exch_args(h, level, y, x, b, 1.0, m.d_partials + kCellWaves * ca.nblocks, R);
+  ea.d = d;
+  ea.c1 = c1;
+  ea.c2 = c2;
+  if (ea.total > 0) {
+    Prof p(h, "exchange", s);
+    launch_exchange(dtype, OP_CHEB, ea, s);
+    check_launch();
+  }
+}
+
+// `count` smoother applications between two buffers; returns the buffer
+// holding the result.
+static void* smooth(ht_mesh* h, int level, int dtype, const ht_cycle_opts& o,
+                    int count, void* cur, void* other, const void* b,
+                    hipStream_t s) {
+  if (o.smoother == HT_SMOOTH_JACOBI)
+    return sweeps(h, level, dtype, o.omega, count, cur, other, b, s);
+  const double beta = 1.1 * h->lambda_max.at(level), alpha = beta / 8.0;
+  const double theta = 0.5 * (beta + alpha), delta = 0.5 * (beta - alpha);
+  const double sigma = theta / delta;
+  void* d = work(h, level, dtype).d;
+  for (int app = 0; app < count; ++app) {
+    double rho_prev = 1.0 / sigma;
+    for (int k = 0; k < o.degree; ++k) {
+      double c1 = 0.0, c2 = 1.0 / theta;
+      if (k > 0) {
+        const double rho = 1.0 / (2.0 * sigma - rho_prev);
+        c1 = rho * rho_prev;
+        c2 = 2.0 * rho / delta;
+        rho_prev = rho;
+      }
+      cheb_pass(h, level, dtype, cur, other, b, d, c1, c2, s);
+      std::swap(cur, other);
+    }
+  }
+  return cur;
 }
 
 // Top-level V-cycle on caller buffers (u, b).
@@ -729,7 +853,9 @@ int ht_mesh_destroy(ht_mesh* h) {
       for (auto* p : m.d_w64) if (p) (void)hipFree(p);
       for (auto* p : m.d_w32) if (p) (void)hipFree(p);
       for (auto* list : {&m.work64, &m.work32})
-        for (auto& w : *list) { (void)hipFree(w.u); (void)hipFree(w.b); (void)hipFree(w.t); }
+        for (auto& w : *list) {
+          (void)hipFree(w.u); (void)hipFree(w.b); (void)hipFree(w.t); (void)hipFree(w.d);
+        }
       for (auto& kv : m.coarse) {
         (void)hipFree(kv.second.d_inv); (void)hipFree(kv.second.d_owner);
         (void)hipFree(kv.second.d_copy_ptr); (void)hipFree(kv.second.d_copy_slot);
@@ -1016,6 +1142,7 @@ int ht_vcycle(ht_mesh* h, int level, int dtype, const ht_cycle_opts* o, void* u,
         throw Error{HT_ERR_HIP, g_last_error};
       return;
     }
+    prepare_smoother(h, level, dtype, *o, s);
     vcycle_top(h, level, dtype, *o, u, b, false, s);
   });
 }
@@ -1056,7 +1183,8 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
     // cycle's graph ends with that sweep instead of a separate residual
     // pass; when the norm meets the tolerance the sweep is discarded and u
     // is the result.
-    const bool lag = !mixed && o->cyc.nu1 > 0 && level > o->cyc.coarse_level;
+    const bool lag = !mixed && o->cyc.nu1 > 0 && level > o->cyc.coarse_level &&
+                     o->cyc.smoother == HT_SMOOTH_JACOBI;
     auto first_sweep = [&](hipStream_t ss) {
       op_pass(h, level, HT_F64, OP_JACOBI, u, w64.t, b, o->cyc.omega, ss, true, 0);
       HT_CHECK_HIP(hipMemcpyAsync(h->m.h_scalar, h->m.d_scalar, sizeof(double),
@@ -1086,13 +1214,14 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
     std::ostringstream key;
     key << "solve:" << level << ':' << o->precision << ':' << o->cyc.nu1 << ':'
         << o->cyc.nu2 << ':' << o->cyc.omega << ':' << o->cyc.coarse_level << ':'
-        << u << ':' << b;
+        << o->cyc.smoother << ':' << o->cyc.degree << ':' << u << ':' << b;
     // all allocations and host setup happen before any capture
     coarse_solver(h, o->cyc.coarse_level);
     for (int l = o->cyc.coarse_level; l <= level; ++l) {
       work(h, l, HT_F64);
       if (mixed) work(h, l, HT_F32);
     }
+    prepare_smoother(h, level, mixed ? HT_F32 : HT_F64, o->cyc, s);
     if (lag && rel > o->rel_tol && k < o->max_cycles && std::isfinite(rel)) {
       first_sweep(s);
       HT_CHECK_HIP(hipStreamSynchronize(s));
@@ -1116,6 +1245,14 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
   return rc;
 }
 
+int ht_lambda_max(ht_mesh* h, int level, double* lambda, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, HT_F64);
+    if (!lambda) throw Error{HT_ERR_ARG, "lambda is NULL"};
+    *lambda = lambda_max_of(h, level, s);
+  });
+}
+
 int ht_fmg(ht_mesh* h, int level, const ht_cycle_opts* o, int cycles, void* u,
            const void* b, double* rel_res, ht_stream stream) {
   return guard([&] {
@@ -1128,6 +1265,7 @@ int ht_fmg(ht_mesh* h, int level, const ht_cycle_opts* o, int cycles, void* u,
     // set-up before capture: workspace and the coarse solver
     coarse_solver(h, lc);
     for (int l = lc; l <= level; ++l) work(h, l, HT_F64);
+    prepare_smoother(h, level, HT_F64, *o, s);
     auto body = [&](hipStream_t ss) {
       const Range R = full_range(h->m);
       // right-hand sides of the coarser levels: b_{l-1} = R b_l
@@ -1156,7 +1294,8 @@ int ht_fmg(ht_mesh* h, int level, const ht_cycle_opts* o, int cycles, void* u,
     };
     std::ostringstream key;
     key << "fmg:" << level << ':' << o->nu1 << ':' << o->nu2 << ':' << o->omega << ':'
-        << lc << ':' << cycles << ':' << u << ':' << b;
+        << lc << ':' << o->smoother << ':' << o->degree << ':' << cycles << ':' << u
+        << ':' << b;
     run_graph(h, key.str(), body, s);
     if (rel_res) {
       const double bn = norm_of(h, level, HT_F64, b, b, s, true);
@@ -1264,6 +1403,8 @@ int ht_batch_solve(ht_batch* B, const ht_solve_opts* o, void* const* u,
     const int P = bt.nprob;
     if (o->precision != HT_PREC_F64)
       throw Error{HT_ERR_ARG, "batch solves run in FP64 (HT_PREC_F64)"};
+    if (o->cyc.smoother != HT_SMOOTH_JACOBI)
+      throw Error{HT_ERR_ARG, "batch solves use the Jacobi smoother"};
     if (o->max_cycles < 0 || o->max_cycles > 256)
       throw Error{HT_ERR_ARG, "max_cycles must be in [0, 256]"};
     check_cycle(m, bt.lmax, &o->cyc);

@@ -87,6 +87,7 @@ struct LevelWork {
   void* u = nullptr;    // correction / iterate on coarse levels
   void* b = nullptr;    // right-hand side on coarse levels
   void* t = nullptr;    // Jacobi ping-pong and residual
+  void* d = nullptr;    // Chebyshev direction (allocated when used)
 };
 
 // Exact coarse-level solver: A_II^-1 as dense blocks, one per independent

@@ -191,6 +191,9 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
       make_rsrc((T*)a.y + cell * ostride, ostride * (int64_t)sizeof(T));
   const __amdgpu_buffer_rsrc_t rb =
       make_rsrc(a.b ? (const T*)a.b + cell * a.stride : (const T*)a.y, bytes);
+  constexpr bool CHEB = (OP == OP_CHEB);
+  const __amdgpu_buffer_rsrc_t rd =
+      make_rsrc(CHEB ? (T*)a.d + cell * a.stride : (T*)a.y, bytes);
   T w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0, w6 = 0, w7 = 0, w8 = 0,
     w9 = 0, w10 = 0, w11 = 0, w12 = 0, w13 = 0, w14 = 0;
   unsigned own16 = 0;
@@ -273,7 +276,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
     }
   };
 
-  constexpr bool NEED_B = (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32);
+  constexpr bool NEED_B =
+      (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32 || OP == OP_CHEB);
   const __amdgpu_buffer_rsrc_t ry32 = make_rsrc(
       OP == OP_RESID32 ? (float*)a.y32 + cell * a.stride : (float*)a.y,
       a.stride * (int64_t)sizeof(float));
@@ -283,13 +287,23 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   // so the four plane buffers rotate by renaming, not by register moves.
   auto step = [&](int k, T (&pm)[J + 2], T (&pc)[J + 2], T (&pp)[J + 2],
                   T (&pn)[J + 2], unsigned (&oc)[J + 2], unsigned (&op)[J + 2],
-                  unsigned (&on)[J + 2], T (&bc)[J], T (&bp)[J]) {
+                  unsigned (&on)[J + 2], T (&bc)[J], T (&bp)[J], T (&dc)[J],
+                  T (&dp)[J]) {
     plane_offsets(on);
 #pragma unroll
     for (int r = 0; r < J + 2; ++r) bload(pn[r], rx, on[r]);
     if (NEED_B) {
 #pragma unroll
       for (int r = 0; r < J; ++r) bload(bp[r], rb, op[r + 1]);
+    }
+    if (CHEB) {
+      // the first step of an application has c1 = 0: d is not read
+#pragma unroll
+      for (int r = 0; r < J; ++r) dp[r] = (T)0;
+      if (a.c1 != 0.0) {
+#pragma unroll
+        for (int r = 0; r < J; ++r) bload(dp[r], rd, op[r + 1]);
+      }
     }
     mask_plane(k + 1, pp);
     if (RESTR && (k & 1)) return;
@@ -398,6 +412,11 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
           out = surf ? acc : r;
         } else if (OP == OP_JACOBI) {
           out = surf ? acc : fma(omega_invd, r, c);
+        } else if (OP == OP_CHEB) {
+          // omega = 1: omega_invd is the inverse diagonal
+          const T dn = fma((T)a.c1, dc[rr], (T)a.c2 * (omega_invd * r));
+          out = surf ? acc : c + dn;
+          bstore(dn, rd, surf ? HT_OOB : so);
         }
         if (OP == OP_RESID32) {
           // finished points: FP32 residual (element offset = so / 2);
@@ -413,7 +432,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
 
   T PA[J + 2], PB[J + 2], PC[J + 2], PD[J + 2];
   unsigned OA[J + 2], OB[J + 2], OC[J + 2], OD[J + 2];
-  T BA[J], BB[J];
+  T BA[J], BB[J], DA[J], DB[J];
   plane_offsets(OB);
   plane_offsets(OC);
 #pragma unroll
@@ -427,16 +446,24 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
 #pragma unroll
     for (int r = 0; r < J; ++r) bload(BA[r], rb, OB[r + 1]);
   }
+  if (CHEB) {
+#pragma unroll
+    for (int r = 0; r < J; ++r) DA[r] = (T)0;
+    if (a.c1 != 0.0) {
+#pragma unroll
+      for (int r = 0; r < J; ++r) bload(DA[r], rd, OB[r + 1]);
+    }
+  }
   mask_plane(0, PB);
   const int kmax = n - i0 - j0;
   for (int k = 0; k <= kmax; k += 4) {
-    step(k, PA, PB, PC, PD, OB, OC, OD, BA, BB);
+    step(k, PA, PB, PC, PD, OB, OC, OD, BA, BB, DA, DB);
     if (k + 1 > kmax) break;
-    step(k + 1, PB, PC, PD, PA, OC, OD, OA, BB, BA);
+    step(k + 1, PB, PC, PD, PA, OC, OD, OA, BB, BA, DB, DA);
     if (k + 2 > kmax) break;
-    step(k + 2, PC, PD, PA, PB, OD, OA, OB, BA, BB);
+    step(k + 2, PC, PD, PA, PB, OD, OA, OB, BA, BB, DA, DB);
     if (k + 3 > kmax) break;
-    step(k + 3, PD, PA, PB, PC, OA, OB, OC, BB, BA);
+    step(k + 3, PD, PA, PB, PC, OA, OB, OC, BB, BA, DB, DA);
   }
   if (NEED_B) {
     nsq = wave_sum(nsq);
@@ -525,7 +552,7 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       }
       T val;
       if (P.boundary) {
-        val = (OP == OP_JACOBI) ? ((const T*)a.u)[s0] : (T)0;
+        val = (OP == OP_JACOBI || OP == OP_CHEB) ? ((const T*)a.u)[s0] : (T)0;
       } else if (OP == OP_RESID || OP == OP_RESID32) {
         val = ((const T*)a.b)[s0] - sum;
         nsq = (double)val * (double)val;
@@ -534,6 +561,15 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
         const T r = ((const T*)a.b)[s0] - sum;
         nsq = (double)r * (double)r;
         val = ((const T*)a.u)[s0] + (T)a.omega * invd * r;
+      } else if (OP == OP_CHEB) {
+        const T invd = (T)(a.nscale * P.inv_diag_unit);
+        const T r = ((const T*)a.b)[s0] - sum;
+        nsq = (double)r * (double)r;
+        T* d = (T*)a.d;
+        const T dn = fma((T)a.c1, a.c1 != 0.0 ? d[s0] : (T)0, (T)a.c2 * (invd * r));
+        val = ((const T*)a.u)[s0] + dn;
+        d[s0] = dn;
+        for (int q = 1; q < cnt; ++q) d[slot_q(q)] = dn;
       } else {
         val = sum;
       }
@@ -547,7 +583,7 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       }
     }
   }
-  if (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32) {
+  if (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32 || OP == OP_CHEB) {
     __shared__ double red[4];
     nsq = wave_sum(nsq);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nsq;
@@ -783,19 +819,27 @@ __global__ __launch_bounds__(64) void k_elem(ElemArgs a) {
           uint8_t f = (c.flags & kClsOwner) ? HT_SLOT_OWNER : HT_SLOT_GHOST;
           if (c.flags & kClsDirichlet) f |= HT_SLOT_DIRICHLET;
           ((uint8_t*)a.out)[s] = f;
-        } else if (EOP == EOP_COORDS) {
+        } else if (EOP == EOP_COORDS || EOP == EOP_PROBE) {
           const double* X = a.cell_xyz + cell * 12;     // sorted by global id
           const int8_t* ord = a.cell_order + cell * 4;  // local index per sorted
           const int j = j0 + r;
           const int wl[4] = {n - i - j - k, i, j, k};
           T* o = (T*)a.out;
+          double xyz[3];
           for (int a3 = 0; a3 < 3; ++a3) {
             double sum = 0.0;
             for (int q = 0; q < 4; ++q) {
               const int wq = wl[ord[q]];
               if (wq > 0) sum += (double)wq * X[3 * q + a3];
             }
-            o[3 * s + a3] = (T)(sum * a.alpha);
+            xyz[a3] = sum * a.alpha;
+            if (EOP == EOP_COORDS) o[3 * s + a3] = (T)xyz[a3];
+          }
+          if (EOP == EOP_PROBE) {
+            // start vector of the power iteration: a field that oscillates
+            // on the scale of the finest micro-cells, zero on the boundary
+            const double ph = 1000.0 * xyz[0] + 1700.0 * xyz[1] + 2300.0 * xyz[2];
+            o[s] = (c.flags & kClsDirichlet) ? (T)0 : (T)sin(ph);
           }
         }
       }
@@ -899,9 +943,11 @@ void launch_cell(int dtype, int op, int J, const CellArgs& a, hipStream_t s) {
     else if (op == OP_RESID) launch_cell_t<double, OP_RESID>(a, J, s);
     else if (op == OP_JACOBI) launch_cell_t<double, OP_JACOBI>(a, J, s);
     else if (op == OP_RESID32) launch_cell_t<double, OP_RESID32>(a, J, s);
+    else if (op == OP_CHEB) launch_cell_t<double, OP_CHEB>(a, J, s);
     else launch_cell_t<double, OP_RESTRICT>(a, J, s);
   } else {
     if (op == OP_RESID32) throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input"};
+    if (op == OP_CHEB) { launch_cell_t<float, OP_CHEB>(a, J, s); return; }
     if (op == OP_APPLY) launch_cell_t<float, OP_APPLY>(a, J, s);
     else if (op == OP_RESID) launch_cell_t<float, OP_RESID>(a, J, s);
     else if (op == OP_JACOBI) launch_cell_t<float, OP_JACOBI>(a, J, s);
@@ -920,16 +966,19 @@ static void launch_exchange_t(int op, const ExchArgs& a, hipStream_t s) {
     case OP_FILL: hipLaunchKernelGGL((k_exchange<T, OP_FILL>), grid, dim3(256), 0, s, a); break;
     case OP_RESTRICT: hipLaunchKernelGGL((k_exchange<T, OP_RESTRICT>), grid, dim3(256), 0, s, a); break;
     case OP_RESID32: hipLaunchKernelGGL((k_exchange<T, OP_RESID32>), grid, dim3(256), 0, s, a); break;
+    case OP_CHEB: hipLaunchKernelGGL((k_exchange<T, OP_CHEB>), grid, dim3(256), 0, s, a); break;
   }
 }
 void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
   if (a.total <= 0) return;
   if (op != OP_APPLY && op != OP_RESID && op != OP_JACOBI && op != OP_SYNC &&
-      op != OP_FILL && op != OP_RESTRICT && op != OP_RESID32)
+      op != OP_FILL && op != OP_RESTRICT && op != OP_RESID32 && op != OP_CHEB)
     throw Error{HT_ERR_ARG, "unknown exchange operation"};
   // the residual and Jacobi epilogues read u and b at the owner copy
-  if ((op == OP_RESID || op == OP_JACOBI || op == OP_RESID32) && (!a.u || !a.b))
+  if ((op == OP_RESID || op == OP_JACOBI || op == OP_RESID32 || op == OP_CHEB) &&
+      (!a.u || !a.b))
     throw Error{HT_ERR_ARG, "exchange for residual/Jacobi needs u and b"};
+  if (op == OP_CHEB && !a.d) throw Error{HT_ERR_ARG, "Chebyshev step needs d"};
   if (op == OP_RESID32 && (dtype != HT_F64 || !a.y32))
     throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input and y32"};
   if (dtype == HT_F64) launch_exchange_t<double>(op, a, s);
@@ -952,6 +1001,7 @@ static void launch_elem_t(int eop, const ElemArgs& a, hipStream_t s) {
     case EOP_DOT: hipLaunchKernelGGL((k_elem<T, EOP_DOT>), grid, dim3(64), 0, s, a); break;
     case EOP_FLAGS: hipLaunchKernelGGL((k_elem<T, EOP_FLAGS>), grid, dim3(64), 0, s, a); break;
     case EOP_COORDS: hipLaunchKernelGGL((k_elem<T, EOP_COORDS>), grid, dim3(64), 0, s, a); break;
+    case EOP_PROBE: hipLaunchKernelGGL((k_elem<T, EOP_PROBE>), grid, dim3(64), 0, s, a); break;
   }
 }
 void launch_elem(int dtype, int eop, const ElemArgs& a, hipStream_t s) {

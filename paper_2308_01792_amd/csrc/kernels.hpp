@@ -11,10 +11,12 @@ namespace ht {
 // cell kernel writes finished points straight to y32 and FP64 partial rows
 // of surface points to y; the exchange completes those in FP64 and writes
 // y32.
+// OP_CHEB: one step of the Chebyshev iteration on D^-1 A:
+// d <- c1 d + c2 D^-1 (b - A x) (in place), y = x + d.
 enum { OP_APPLY = 0, OP_RESID = 1, OP_JACOBI = 2, OP_SYNC = 3, OP_FILL = 4,
-       OP_RESTRICT = 5, OP_RESID32 = 6 };
+       OP_RESTRICT = 5, OP_RESID32 = 6, OP_CHEB = 7 };
 enum { EOP_ZERO_GUESS = 0, EOP_MASS = 1, EOP_ZERO_INTERIOR = 2, EOP_DOT = 3,
-       EOP_FLAGS = 4, EOP_COORDS = 5 };
+       EOP_FLAGS = 4, EOP_COORDS = 5, EOP_PROBE = 6 };
 enum { FOP_COPY = 0, FOP_ADD = 1, FOP_ZERO = 2 };
 enum { kMaxInc = 128 };  // incident cells per shared primitive (checked)
 // Waves per stencil-kernel workgroup, stacked in j on one cell: a group
@@ -28,6 +30,8 @@ struct CellArgs {
   const void* x;        // operand (u for residual / Jacobi)
   void* y;              // output
   void* y32;            // FP32 residual (OP_RESID32)
+  void* d;              // Chebyshev direction (OP_CHEB), updated in place
+  double c1, c2;        // Chebyshev step coefficients
   const void* b;        // right-hand side (residual / Jacobi)
   const void* w;        // level-scaled class stencils [nc][16][15]
   const ClassInfo* cls; // [nc][16]
@@ -44,6 +48,8 @@ struct CellArgs {
 struct ExchArgs {
   void* y;
   void* y32;            // FP32 residual (OP_RESID32)
+  void* d;              // Chebyshev direction (OP_CHEB)
+  double c1, c2;
   const void* u;
   const void* b;
   const DevPrim* prim;

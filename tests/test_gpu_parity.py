@@ -343,3 +343,49 @@ def test_fmg_matches_oracle(cycles):
     assert rel_err(P.from_gpu(4, ug), uo) <= 1e-11
     ro = np.linalg.norm(S.residual(uo, b)) / np.linalg.norm(b[S.interior])
     assert rel == pytest.approx(ro, rel=1e-6)
+
+
+def test_lambda_max_matches_oracle():
+    """Power-iteration estimate of the largest eigenvalue of D^-1 A (the
+    Chebyshev smoother's interval): same start field, same iteration."""
+    from oracle.mg import lambda_max_estimate
+    for name, level in (("jittered_288", 4), ("slab_3_11", 3)):
+        P = pair(name, level, 2 if level > 2 else level)
+        assert P.m.lambda_max(level) == pytest.approx(
+            lambda_max_estimate(P.S(level)), rel=1e-9)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-5)])
+@pytest.mark.parametrize("nu,degree", [((1, 1), 2), ((2, 1), 3)])
+def test_vcycle_chebyshev_iterates(dtype, tol, nu, degree):
+    """V-cycles with the Chebyshev smoother: every iterate against the
+    oracle's."""
+    P = pair("jittered_288", 4, 2)
+    S = P.S(4)
+    b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    bg = P.to_gpu(4, b, tdt)
+    ug = torch.zeros_like(bg)
+    uo = np.zeros_like(b)
+    bo = b.astype(np.float32).astype(np.float64) if dtype == "f32" else b
+    for _ in range(3):
+        P.m.vcycle(4, ug, bg, nu[0], nu[1], coarse_level=2,
+                   smoother=ht.HT_SMOOTH_CHEBYSHEV, degree=degree)
+        uo = P.H.vcycle(4, uo, bo, nu[0], nu[1], coarse_level=2,
+                        smoother="chebyshev", degree=degree)
+        assert rel_err(P.from_gpu(4, ug), uo) <= tol
+
+
+def test_solve_chebyshev_smoother():
+    P = pair("jittered_288", 4, 2)
+    S = P.S(4)
+    b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5)
+    bg = P.to_gpu(4, b)
+    ug = torch.zeros_like(bg)
+    st = P.m.solve(4, ug, bg, ht.HT_PREC_F64, 1e-10, 100, nu1=1, nu2=1,
+                   smoother=ht.HT_SMOOTH_CHEBYSHEV, degree=2)
+    uo, _ = P.H.solve(4, b, rel_tol=1e-12, coarse_level=2)
+    assert st["converged"] and st["cycles"] <= 20
+    assert rel_err(P.from_gpu(4, ug), uo) <= 1e-8
+    h = np.array(st["history"])
+    assert (h[1:] / h[:-1]).max() < 0.35
