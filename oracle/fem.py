@@ -12,6 +12,13 @@ the interior unknowns.
 
 Lumped mass: m_i = sum over micro-tets T containing i of |T| / 4, the row sums
 of the consistent P1 mass matrix.
+
+Variable coefficient (Section 5.2.1, the div(k grad) element-wise operator of
+the operator catalogue): a_ij = sum over T of the integral over T of
+k grad(phi_i) . grad(phi_j).  The coefficient k is given by its values at the
+micro-vertices and enters as its linear interpolant; the element integral of
+k is taken with a degree-3 quadrature rule on the tetrahedron (the "q3" of the
+form's name), exact for this integrand.
 """
 from __future__ import annotations
 
@@ -38,6 +45,24 @@ def barycentric_gradients(P: np.ndarray):
     return G, vol
 
 
+# Degree-3 rule on a tetrahedron: the centroid with weight -4/5 and the four
+# points with barycentric coordinates (1/2, 1/6, 1/6, 1/6) and permutations,
+# weight 9/20 each (weights relative to the volume; they sum to one).
+TET_Q3_POINTS = np.array([[0.25, 0.25, 0.25, 0.25],
+                          [0.5, 1 / 6, 1 / 6, 1 / 6],
+                          [1 / 6, 0.5, 1 / 6, 1 / 6],
+                          [1 / 6, 1 / 6, 0.5, 1 / 6],
+                          [1 / 6, 1 / 6, 1 / 6, 0.5]])
+TET_Q3_WEIGHTS = np.array([-0.8, 0.45, 0.45, 0.45, 0.45])
+
+
+def element_coefficient_mean(kv: np.ndarray) -> np.ndarray:
+    """(1/|T|) times the integral over T of the linear interpolant of k, by
+    the degree-3 rule.  ``kv``: [M, 4] coefficient values at the vertices."""
+    at_points = kv @ TET_Q3_POINTS.T          # [M, 5] k at the rule's points
+    return at_points @ TET_Q3_WEIGHTS
+
+
 def element_stiffness(P: np.ndarray):
     """Local stiffness matrices K_T[q, r] = |T| grad(l_q) . grad(l_r)."""
     G, vol = barycentric_gradients(P)
@@ -46,13 +71,17 @@ def element_stiffness(P: np.ndarray):
 
 
 class P1System:
-    """Assembled P1 Laplacian of one micro-mesh, with boundary and mass."""
+    """Assembled P1 stiffness matrix of one micro-mesh, with boundary and
+    mass: the Laplacian, or div(k grad) when ``kappa`` (values of k at the
+    micro-vertices, canonical key order) is given."""
 
-    def __init__(self, mesh: MicroMesh):
+    def __init__(self, mesh: MicroMesh, kappa: np.ndarray | None = None):
         self.mesh = mesh
         N = mesh.num_vertices
         P = mesh.xyz[mesh.tets]
         K, vol = element_stiffness(P)
+        if kappa is not None:
+            K = K * element_coefficient_mean(kappa[mesh.tets])[:, None, None]
         rows = np.repeat(mesh.tets, 4, axis=1).ravel()
         cols = np.tile(mesh.tets, (1, 4)).ravel()
         self.A = sp.coo_matrix((K.ravel(), (rows, cols)),

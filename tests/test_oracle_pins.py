@@ -558,3 +558,76 @@ def test_c1_lattice_stencil_reproduces_oracle():
         ul = np.where(inner, ul + (2 / 3) * (b - lattice_apply(ul)) / diag, ul)
     uo = S.jacobi(uo, b, 2 / 3, sweeps=10)
     assert np.abs(ul - uo).max() < 1e-14
+
+
+# ----------------------------------------------- variable coefficient --
+def test_q3_rule_integrates_cubics_exactly():
+    """The degree-3 rule against the closed form of monomial integrals over
+    the unit simplex: a! b! c! / (a + b + c + 3)!, times 3! for the volume
+    normalisation.  A wrong weight or point breaks some monomial."""
+    from math import factorial
+    from oracle.fem import TET_Q3_POINTS, TET_Q3_WEIGHTS
+    # reference tet with vertices 0, e1, e2, e3: x = lambda_1 .. lambda_3
+    X = TET_Q3_POINTS[:, 1:]
+    for a in range(4):
+        for b in range(4 - a):
+            for c in range(4 - a - b):
+                quad = (TET_Q3_WEIGHTS * X[:, 0] ** a * X[:, 1] ** b *
+                        X[:, 2] ** c).sum() / 6.0
+                exact = factorial(a) * factorial(b) * factorial(c) / \
+                    factorial(a + b + c + 3)
+                assert abs(quad - exact) <= 1e-15, (a, b, c)
+    # and it is not exact beyond degree 3
+    quad4 = (TET_Q3_WEIGHTS * X[:, 0] ** 4).sum() / 6.0
+    assert abs(quad4 - factorial(4) / factorial(7)) > 1e-6
+
+
+def test_constant_coefficient_scales_the_laplacian():
+    mesh = MicroMesh(*mesh_by_name("jittered_222"), 2)
+    A = P1System(mesh).A
+    Ak = P1System(mesh, kappa=np.full(mesh.num_vertices, 3.7)).A
+    assert abs(Ak - 3.7 * A).max() <= 1e-14 * abs(Ak).max()
+
+
+@pytest.mark.parametrize("name,level", [("jittered_222", 2), ("ref_tet", 3)])
+def test_affine_coefficient_uses_the_centroid_value(name, level):
+    """For affine k the element integral is |T| k(centroid) exactly.  The
+    reference assembly evaluates k at each micro-tet's centroid from the
+    coordinates (no vertex values, no quadrature) and scales the Laplacian's
+    element matrices by it, via the independent nodal-basis construction."""
+    mesh = MicroMesh(*mesh_by_name(name), level)
+    g, c0 = np.array([0.4, -0.3, 0.25]), 1.3
+    kv = mesh.xyz @ g + c0
+    S = P1System(mesh, kappa=kv)
+    N = mesh.num_vertices
+    A = np.zeros((N, N))
+    for t in mesh.tets:
+        P = mesh.xyz[t]
+        grads = np.linalg.solve(np.hstack([P, np.ones((4, 1))]), np.eye(4))[:3].T
+        vol = abs(np.linalg.det(P[1:] - P[0])) / 6
+        kc = P.mean(axis=0) @ g + c0
+        A[np.ix_(t, t)] += kc * vol * grads @ grads.T
+    assert np.abs(A - S.A.toarray()).max() <= 1e-13 * np.abs(A).max()
+
+
+def test_coefficient_energy_identity():
+    """u^T A_k u = sum over T of (integral of k over T) |grad u_T|^2, with
+    grad u_T solved from T's edge vectors; the integral of the linear
+    interpolant of k is |T| times the vertex mean.  Also: symmetric, rows sum
+    to zero, positive definite on the interior unknowns."""
+    mesh = MicroMesh(*mesh_by_name("jittered_288"), 1)
+    kv = fields.coefficient_field(mesh.xyz)
+    S = P1System(mesh, kappa=kv)
+    u = fields.uniform_values(mesh.num_vertices, seed=21)
+    energy = 0.0
+    for t in mesh.tets:
+        P = mesh.xyz[t]
+        grad = np.linalg.solve(P[1:] - P[0], u[t[1:]] - u[t[0]])
+        vol = abs(np.linalg.det(P[1:] - P[0])) / 6
+        energy += vol * kv[t].mean() * grad @ grad
+    assert abs(u @ (S.A @ u) - energy) <= 1e-12 * energy
+    A = S.A
+    assert abs(A - A.T).max() <= 1e-15 * abs(A).max()
+    assert np.abs(A @ np.ones(A.shape[0])).max() <= 1e-13 * abs(A).max()
+    AII, _ = S.interior_matrix()
+    np.linalg.cholesky(AII.toarray())

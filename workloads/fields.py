@@ -44,3 +44,11 @@ def smooth_field(xyz: np.ndarray, seed, terms: int = 4) -> np.ndarray:
     for t in range(terms):
         out += amp[t] * np.cos(xyz @ k[t] + phase[t])
     return out
+
+
+def coefficient_field(xyz: np.ndarray) -> np.ndarray:
+    """Diffusion coefficient k(x, y, z) = 1 + sin(2 pi x) sin(2 pi y)
+    sin(2 pi z) / 2, between 1/2 and 3/2."""
+    x, y, z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    return 1.0 + 0.5 * (np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) *
+                        np.sin(2 * np.pi * z))
