@@ -59,7 +59,7 @@ def measured_traffic(kernel: str):
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp"):
+    for f in ("kernels.hip", "kernels.hpp", "device.hpp"):
         with open(os.path.join(ROOT, "paper_2308_01792_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if rec.get("sources_sha256") != h.hexdigest() or rec.get("kernel") != kernel:

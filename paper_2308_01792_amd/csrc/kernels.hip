@@ -11,125 +11,15 @@
 //      operation's epilogue and writes the result into every copy.
 #include <hip/hip_runtime.h>
 
-#include "kernels.hpp"
+#include "device.hpp"
 
 namespace ht {
-
-// 32-bit index arithmetic for device code.  A cell block holds fewer than
-// 2^31 elements up to level 10 (w (w+1) (w+2) <= 1025 * 1026 * 1027 <
-// 2^31), so the tetrahedral and triangular numbers of index.hpp are formed
-// without 64-bit multiplies and divisions.
-__device__ __forceinline__ int tet32(int w) { return w <= 0 ? 0 : w * (w + 1) * (w + 2) / 6; }
-__device__ __forceinline__ int tri32(int w) { return w <= 0 ? 0 : w * (w + 1) / 2; }
-__device__ __forceinline__ int tw32(int w, int i, int j, int k) {
-  return tet32(w) - tet32(w - k) + tri32(w - k) - tri32(w - k - j) + i;
-}
-__device__ __forceinline__ int t2w32(int w, int j, int k) {
-  return tri32(w) - tri32(w - k) + j;
-}
-
-// ------------------------------------------------------- lane exchange --
-// DPP wave shifts (GFX9 family): wave_shr:1 gives lane L the value of lane
-// L-1, wave_shl:1 the value of lane L+1.  With bound_ctrl set, lanes shifted
-// in from outside the wave read 0 and no "old" value has to be materialised.
-__device__ __forceinline__ int dpp_prev(int v) {
-  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
-}
-__device__ __forceinline__ int dpp_next(int v) {
-  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);
-}
-__device__ __forceinline__ float lane_prev(float v) {
-  return __int_as_float(dpp_prev(__float_as_int(v)));
-}
-__device__ __forceinline__ float lane_next(float v) {
-  return __int_as_float(dpp_next(__float_as_int(v)));
-}
-__device__ __forceinline__ double lane_prev(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_prev((int)(b & 0xffffffffll));
-  const int hi = dpp_prev((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double lane_next(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = dpp_next((int)(b & 0xffffffffll));
-  const int hi = dpp_next((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Self-test of the lane exchange: out[l] = prev(l), out[64 + l] = next(l).
 __global__ void k_lane_selftest(int* out) {
   const int l = threadIdx.x;
   out[l] = (int)lane_prev((double)(l + 1));
   out[64 + l] = (int)lane_next((float)(l + 1));
-}
-
-// ----------------------------------------------------- closure helpers --
-struct Lay {
-  int n;
-  int64_t stride, off_s0, off_s1;
-};
-__device__ __forceinline__ Lay lay_of(const CellLayout& L) {
-  return Lay{L.n, L.stride, L.off_s0, L.off_s1};
-}
-// Row bases of the three closure blocks for row (j, k).
-struct RowBase {
-  int e;           // last i of the row (n - j - k)
-  int32_t s0, s1;  // offsets of (0, j, k) in S0 and (e, j, k) in S1
-  int32_t m;       // offset of (1, j, k) in M
-};
-__device__ __forceinline__ RowBase row_base(const Lay& L, int j, int k) {
-  RowBase r;
-  const int n = L.n;
-  r.e = n - j - k;
-  r.s0 = (int32_t)(L.off_s0 + t2w32(n + 1, j, k));
-  r.s1 = (int32_t)(L.off_s1 + t2w32(n, j, k));
-  r.m = (int32_t)tw32(n - 1, 0, j, k);
-  return r;
-}
-__device__ __forceinline__ int32_t row_slot(const RowBase& r, int i) {
-  return i == 0 ? r.s0 : (i == r.e ? r.s1 : r.m + i - 1);
-}
-__device__ __forceinline__ int64_t slot_of(const Lay& L, int i, int j, int k) {
-  const int n = L.n;
-  if (i == 0) return L.off_s0 + t2w32(n + 1, j, k);
-  if (i + j + k == n) return L.off_s1 + t2w32(n, j, k);
-  return tw32(n - 1, i - 1, j, k);
-}
-
-template <typename T>
-__device__ __forceinline__ T ldv(const T* p) { return *p; }
-
-// ----------------------------------------------------------- cell kernel --
-// Buffer loads/stores with a per-cell range: an offset at or beyond the range
-// reads 0 and drops the store, which replaces per-lane branches.
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-#define HT_OOB 0x80000000u
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p,
-                                                           int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
-                                           (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ void bload(double& v, __amdgpu_buffer_rsrc_t r,
-                                      unsigned off) {
-  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ void bload(float& v, __amdgpu_buffer_rsrc_t r,
-                                      unsigned off) {
-  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r,
-                                       unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
-}
-__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r,
-                                       unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
 
 // In-face offsets of the face i = 0 (class 1) and of the slanted face
@@ -594,39 +484,22 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
 }
 
 // --------------------------------------------------------- tile walker --
-// Visits the closure points of one (cell, tile): lanes are 64 consecutive
-// i = i0 + lane, rows j0 .. j0 + kWalkRows - 1, planes k = 0 .. n - i0 - j0.
-// f(i, j, k, e, el) gets the line end e = n - j - k and the element offset
-// el of the point inside its cell block (closure layout of index.hpp).
-enum { kWalkRows = 8 };
-template <typename F>
-__device__ __forceinline__ void walk_tile(const Lay& L, int i0, int j0, int i,
-                                          F&& f) {
-  const int n = L.n, w1 = n - 1;
-  const int kmax = n - i0 - j0;
-  for (int k = 0; k <= kmax; ++k) {
-    int mb = (int)(tet32(w1) - tet32(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
-    int sa = (int)L.off_s0 + (int)(tri32(n + 1) - tri32(n + 1 - k)) + j0;
-    int sb = (int)L.off_s1 + (int)(tri32(n) - tri32(n - k)) + j0;
-#pragma unroll
-    for (int r = 0; r < kWalkRows; ++r) {
-      const int j = j0 + r;
-      const int e = n - j - k;
-      if (e < i0) break;
-      if (i <= e) f(i, j, k, e, i == 0 ? sa : (i == e ? sb : mb + i));
-      mb += w1 - k - j;
-      ++sa;
-      ++sb;
-    }
-  }
-}
+// The transfer and elementwise kernels visit the closure points of one
+// (cell, walk tile) per wave: lanes are 64 consecutive i = i0 + lane, rows
+// j0 .. j0 + kWalkRows - 1, planes k = 0 .. n - i0 - j0.  A workgroup holds
+// kWalkWaves waves on consecutive walk tiles, so that enough waves are
+// resident per CU for these streaming kernels.
+enum { kWalkRows = 8, kWalkWaves = 4 };
 
-// Block -> (cell, tile) with the XCD-aware order of the stencil kernel.
+// (block, wave) -> (cell, tile).  Consecutive blocks go to different XCDs;
+// each XCD gets one contiguous run of tiles, as in the stencil kernel.
 __device__ __forceinline__ bool walk_block(int64_t nblocks, int64_t ntiles,
-                                           const int2* tiles, int64_t& cell,
-                                           int& i0, int& j0, int64_t& w) {
-  const int64_t chunk = (nblocks + 7) / 8;
-  w = (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
+                                           const int2* tiles, int wave,
+                                           int64_t& cell, int& i0, int& j0,
+                                           int64_t& w) {
+  const int64_t groups = (nblocks + kWalkWaves - 1) / kWalkWaves;
+  const int64_t chunk = (groups + 7) / 8;
+  w = ((int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8) * kWalkWaves + wave;
   if (w >= nblocks) return false;
   cell = w / ntiles;
   const int2 t = tiles[w % ntiles];
@@ -662,11 +535,12 @@ __device__ __forceinline__ void parity_dir(int p, int& di, int& dj, int& dk) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_prolong(XferArgs a) {
+__global__ __launch_bounds__(64 * kWalkWaves) void k_prolong(XferArgs a) {
   int64_t cell, w;
   int i0, j0;
-  if (!walk_block(a.nblocks, a.ntiles, a.tiles, cell, i0, j0, w)) return;
-  const int lane = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (!walk_block(a.nblocks, a.ntiles, a.tiles, wave, cell, i0, j0, w)) return;
+  const int lane = threadIdx.x & 63;
   const uint8_t fl = lane < 16 ? a.cls[cell * 16 + lane].flags : 0;
   const unsigned dmask = (unsigned)__ballot((fl & kClsDirichlet) != 0) & 0xffffu;
   const Lay Lf{a.nf, a.stride_f, a.off_s0_f, a.off_s1_f};
@@ -739,13 +613,18 @@ __global__ __launch_bounds__(64) void k_prolong(XferArgs a) {
 // all rows of the tile are formed first and every load is issued before any
 // result is used.
 template <typename T, int EOP>
-__global__ __launch_bounds__(64) void k_elem(ElemArgs a) {
+__global__ __launch_bounds__(64 * kWalkWaves) void k_elem(ElemArgs a) {
   int64_t cell, w;
   int i0, j0;
-  if (!walk_block(a.nblocks, a.ntiles, a.tiles, cell, i0, j0, w)) return;
-  __shared__ ClassInfo ci[16];
-  if (threadIdx.x < 16) ci[threadIdx.x] = a.cls[cell * 16 + threadIdx.x];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const bool live = walk_block(a.nblocks, a.ntiles, a.tiles, wave, cell, i0, j0, w);
+  // class table of the wave's cell; every wave reaches the barrier
+  __shared__ ClassInfo cis[kWalkWaves][16];
+  if (live && lane < 16) cis[wave][lane] = a.cls[cell * 16 + lane];
   __syncthreads();
+  if (!live) return;
+  const ClassInfo* ci = cis[wave];
   const Lay L{a.n, a.stride, a.off_s0, a.off_s1};
   const int64_t cb = cell * L.stride;
   const int64_t bytes = L.stride * (int64_t)sizeof(T);
@@ -754,7 +633,7 @@ __global__ __launch_bounds__(64) void k_elem(ElemArgs a) {
   const __amdgpu_buffer_rsrc_t r1 =
       make_rsrc(a.in1 ? (const T*)a.in1 + cb : (const T*)a.out + cb, bytes);
   const __amdgpu_buffer_rsrc_t ro = make_rsrc((T*)a.out + cb, bytes);
-  const int n = L.n, w1 = n - 1, i = i0 + (int)threadIdx.x;
+  const int n = L.n, w1 = n - 1, i = i0 + lane;
   const int kmax = n - i0 - j0;
   double acc = 0.0;
   for (int k = 0; k <= kmax; ++k) {
@@ -847,7 +726,7 @@ __global__ __launch_bounds__(64) void k_elem(ElemArgs a) {
   }
   if (EOP == EOP_DOT) {
     acc = wave_sum(acc);
-    if (threadIdx.x == 0) a.partials[w] = acc;
+    if (lane == 0) a.partials[w] = acc;
   }
 }
 
@@ -985,23 +864,28 @@ void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
   else launch_exchange_t<float>(op, a, s);
 }
 
+static dim3 walk_grid(int64_t nblocks) {
+  const int64_t groups = (nblocks + kWalkWaves - 1) / kWalkWaves;
+  return dim3((unsigned)(((groups + 7) / 8) * 8));
+}
+
 void launch_prolong(int dtype, const XferArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8));
-  if (dtype == HT_F64) hipLaunchKernelGGL(k_prolong<double>, grid, dim3(64), 0, s, a);
-  else hipLaunchKernelGGL(k_prolong<float>, grid, dim3(64), 0, s, a);
+  const dim3 grid = walk_grid(a.nblocks), block(64 * kWalkWaves);
+  if (dtype == HT_F64) hipLaunchKernelGGL(k_prolong<double>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_prolong<float>, grid, block, 0, s, a);
 }
 
 template <typename T>
 static void launch_elem_t(int eop, const ElemArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8));
+  const dim3 grid = walk_grid(a.nblocks), block(64 * kWalkWaves);
   switch (eop) {
-    case EOP_ZERO_GUESS: hipLaunchKernelGGL((k_elem<T, EOP_ZERO_GUESS>), grid, dim3(64), 0, s, a); break;
-    case EOP_MASS: hipLaunchKernelGGL((k_elem<T, EOP_MASS>), grid, dim3(64), 0, s, a); break;
-    case EOP_ZERO_INTERIOR: hipLaunchKernelGGL((k_elem<T, EOP_ZERO_INTERIOR>), grid, dim3(64), 0, s, a); break;
-    case EOP_DOT: hipLaunchKernelGGL((k_elem<T, EOP_DOT>), grid, dim3(64), 0, s, a); break;
-    case EOP_FLAGS: hipLaunchKernelGGL((k_elem<T, EOP_FLAGS>), grid, dim3(64), 0, s, a); break;
-    case EOP_COORDS: hipLaunchKernelGGL((k_elem<T, EOP_COORDS>), grid, dim3(64), 0, s, a); break;
-    case EOP_PROBE: hipLaunchKernelGGL((k_elem<T, EOP_PROBE>), grid, dim3(64), 0, s, a); break;
+    case EOP_ZERO_GUESS: hipLaunchKernelGGL((k_elem<T, EOP_ZERO_GUESS>), grid, block, 0, s, a); break;
+    case EOP_MASS: hipLaunchKernelGGL((k_elem<T, EOP_MASS>), grid, block, 0, s, a); break;
+    case EOP_ZERO_INTERIOR: hipLaunchKernelGGL((k_elem<T, EOP_ZERO_INTERIOR>), grid, block, 0, s, a); break;
+    case EOP_DOT: hipLaunchKernelGGL((k_elem<T, EOP_DOT>), grid, block, 0, s, a); break;
+    case EOP_FLAGS: hipLaunchKernelGGL((k_elem<T, EOP_FLAGS>), grid, block, 0, s, a); break;
+    case EOP_COORDS: hipLaunchKernelGGL((k_elem<T, EOP_COORDS>), grid, block, 0, s, a); break;
+    case EOP_PROBE: hipLaunchKernelGGL((k_elem<T, EOP_PROBE>), grid, block, 0, s, a); break;
   }
 }
 void launch_elem(int dtype, int eop, const ElemArgs& a, hipStream_t s) {
