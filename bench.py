@@ -25,6 +25,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_DOF_F64 = 16.0   # read x, write y per interior DoF
 BYTES_PER_DOF_F32 = 8.0
+# div(k grad): read x and k, write y per interior DoF
+DIVKGRAD_BYTES_PER_DOF = {"f64": 24.0, "f32": 12.0}
+# per point: 24 micro-cells x (3-term coupling sum, 5 flops; coefficient
+# sum, 3; scaled accumulate, 2) + 14 neighbour differences
+DIVKGRAD_FLOPS_PER_DOF = 24 * 10 + 14
+FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
 
 
 def log(msg):
@@ -42,6 +48,7 @@ def parse():
     p.add_argument("--cpu-level", type=int, default=5)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--no-divkgrad", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run 3 plain device copies of one level vector "
                         "(counter calibration for rocprofv3 --pmc)")
@@ -122,6 +129,57 @@ def batch_leg(ht, torch):
                                         for a, b in zip(stb, stl)),
             "max_rel_diff_vs_loop": diff,
             "create_seconds": round(create_s, 3)}
+
+
+def divkgrad_leg(mesh, L, x, ndof, args, stream):
+    """Element-wise div(k grad) apply at the headline size, FP64 and FP32,
+    with k = 1 + sin(2 pi x) sin(2 pi y) sin(2 pi z) / 2 evaluated at the
+    slot coordinates."""
+    import math
+    import torch
+    xyz = torch.empty((x.numel(), 3), dtype=torch.float64, device=x.device)
+    mesh.coords_device(L, xyz)
+    w = 2.0 * math.pi
+    kap = 1.0 + 0.5 * (torch.sin(w * xyz[:, 0]) * torch.sin(w * xyz[:, 1]) *
+                       torch.sin(w * xyz[:, 2]))
+    del xyz
+    res = {}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        k_, x_ = kap.to(dt), x.to(dt)
+        y_ = torch.zeros_like(x_)
+        for _ in range(args.warmup):
+            mesh.apply_divkgrad(L, k_, x_, y_)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            mesh.apply_divkgrad(L, k_, x_, y_)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        mesh.profile(True)
+        mesh.profile_reset()
+        for _ in range(args.steps):
+            mesh.apply_divkgrad(L, k_, x_, y_)
+        torch.cuda.synchronize()
+        cms, cn = mesh.profile_query("cell_divkgrad")
+        mesh.profile(False)
+        cell = cms / cn
+        gbs = DIVKGRAD_BYTES_PER_DOF[name] * ndof / (cell * 1e-3) / 1e9
+        tfl = DIVKGRAD_FLOPS_PER_DOF * ndof / (cell * 1e-3) / 1e12
+        peak = FP64_PEAK_TFLOPS if name == "f64" else FP32_PEAK_TFLOPS
+        res[name] = {"ms": round(ms, 4), "gdofs": round(ndof / (ms * 1e-3) / 1e9, 3),
+                     "cell_kernel_ms": round(cell, 4),
+                     "algorithmic_gbs": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "tflops": round(tfl, 2),
+                     "valu_frac": round(tfl / peak, 4)}
+        log(f"div(k grad) apply {name}: {ms:.3f} ms/step "
+            f"({res[name]['gdofs']:.1f} GDoF/s), cell kernel {cell:.3f} ms, "
+            f"{gbs:.0f} GB/s, {tfl:.1f} TFLOP/s")
+        del k_, x_, y_
+    del kap
+    return res
 
 
 def cpu_baseline(level: int, budget_s: float):
@@ -279,6 +337,10 @@ def main():
                       "hbm_frac": round(ndof * BYTES_PER_DOF_F32 / (ms32 * 1e-3)
                                         / 1e9 / HBM_PEAK_GBS, 4)},
     }
+
+    # ---------------- variable coefficient: div(k grad) apply -------------
+    if not args.no_divkgrad:
+        out["divkgrad_apply"] = divkgrad_leg(mesh, L, x, ndof, args, stream)
 
     # ---------------- solves to 1e-10 --------------------------------------
     if not args.no_solve:

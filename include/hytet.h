@@ -179,6 +179,18 @@ int ht_copy(ht_mesh* mesh, int level, int dtype, const void* src, void* dst,
  * alias. */
 int ht_apply(ht_mesh* mesh, int level, int dtype, const void* x, void* y,
              ht_stream stream);
+/* y = A_k x for the variable-coefficient operator div(k grad) of the
+ * paper's operator catalogue (Section 5.2.1, evaluated element by element):
+ * a_ij = sum over micro-tets T of the integral over T of
+ * k grad(phi_i) . grad(phi_j), with k the P1 field whose point values are
+ * `kappa` (same layout and dtype as x, all copies consistent, e.g. after
+ * ht_sync); the linear interpolant of k is integrated exactly, so T
+ * contributes the mean of k at its vertices times its element matrix.
+ * y = 0 at Dirichlet micro-vertices; Dirichlet values of x act as data.
+ * The library keeps per-level couplings (36 values per cell) after the first
+ * call on a level.  y must not alias x or kappa. */
+int ht_apply_divkgrad(ht_mesh* mesh, int level, int dtype, const void* kappa,
+                      const void* x, void* y, ht_stream stream);
 /* r = b - A u (0 at Dirichlet); if norm != NULL, also ||r||_2 over unique
  * non-Dirichlet micro-vertices (synchronises the stream). */
 int ht_residual(ht_mesh* mesh, int level, int dtype, const void* u,

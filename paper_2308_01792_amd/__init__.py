@@ -172,6 +172,16 @@ class Mesh:
                               _stream()))
         return y
 
+    def apply_divkgrad(self, level: int, kappa, x, y):
+        """y = A_k x, the div(k grad) operator with k given by its values at
+        the slots (consistent copies); y = 0 at Dirichlet slots."""
+        if kappa.dtype != x.dtype:
+            raise ValueError("kappa and x must have the same dtype")
+        check(load().ht_apply_divkgrad(self._h, level, _dtype_code(x),
+                                       _ptr(kappa), _ptr(x), _ptr(y),
+                                       _stream()))
+        return y
+
     def residual(self, level: int, u, b, r, want_norm: bool = False):
         nrm = C.c_double()
         check(load().ht_residual(self._h, level, _dtype_code(u), _ptr(u),

@@ -70,6 +70,7 @@ SIGNATURES = {
     "ht_dot": (I, [P, I, I, P, P, C.POINTER(D), P]),
     "ht_copy": (I, [P, I, I, P, P, P]),
     "ht_apply": (I, [P, I, I, P, P, P]),
+    "ht_apply_divkgrad": (I, [P, I, I, P, P, P, P]),
     "ht_residual": (I, [P, I, I, P, P, P, C.POINTER(D), P]),
     "ht_smooth_jacobi": (I, [P, I, I, D, I, P, P, P]),
     "ht_restrict": (I, [P, I, I, P, P, P]),

@@ -12,6 +12,7 @@
 
 #include "hytet_impl.hpp"
 #include "kernels.hpp"
+#include "vcoef.hpp"
 
 struct ht_mesh;
 namespace ht {
@@ -196,6 +197,8 @@ void ensure_uploaded_h(ht_mesh* h) {
   m.d_cell_order = upload(co);
   m.d_w64.assign(m.max_level + 1, nullptr);
   m.d_w32.assign(m.max_level + 1, nullptr);
+  m.d_kc64.assign(m.max_level + 1, nullptr);
+  m.d_kc32.assign(m.max_level + 1, nullptr);
   int64_t pcap = 0;
   for (int l = m.min_level; l <= m.max_level; ++l) {
     std::vector<double> w;
@@ -352,6 +355,66 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
                     bool want_norm = false, int scalar_slot = 0) {
   op_pass(h, level, dtype, op, x, y, b, omega, s, want_norm, scalar_slot,
           full_range(h->m));
+}
+
+// ------------------------------------------- variable coefficient -------
+// Tile rows of the div(k grad) kernel: two rows per wave keep the planes of
+// x and k and the 24 micro-cell sums within the register file.
+static const int kVcoefJ = 2;
+
+// Level-scaled couplings of the six shapes per cell, K_t / (4 n): the 1/4
+// turns the sum of k over a micro-cell's vertices into their mean, and the
+// micro-cells of level l are the unit shapes scaled by 1/n.
+static const void* vcoef_couplings(ht_mesh* h, int level, int dtype) {
+  Mesh& m = h->m;
+  if (!m.d_kc64[level]) {
+    const double sc = 1.0 / (4.0 * (double)(1 << level));
+    std::vector<double> k(m.nc * kVcoefPerCell);
+    for (int64_t c = 0; c < m.nc; ++c)
+      for (int t = 0; t < 6; ++t)
+        for (int p = 0; p < 6; ++p) k[c * kVcoefPerCell + 6 * t + p] = m.cells[c].shape_k[t][p] * sc;
+    std::vector<float> kf(k.begin(), k.end());
+    m.d_kc64[level] = upload(k);
+    m.d_kc32[level] = upload(kf);
+  }
+  return dtype == HT_F64 ? (const void*)m.d_kc64[level] : (const void*)m.d_kc32[level];
+}
+
+static const std::pair<int2*, int64_t>& tiles_of(ht_mesh* h, int level, int J) {
+  auto it = h->tiles.find({level, J});
+  if (it == h->tiles.end()) {
+    auto t = make_tiles(1 << level, J);
+    it = h->tiles.emplace(std::make_pair(level, J), std::make_pair(upload(t), (int64_t)t.size())).first;
+  }
+  return it->second;
+}
+
+// y = A_k x: cell kernel (full rows inside, partial rows on the surface),
+// then the exchange sums the partial rows (zero at Dirichlet points).
+static void vcoef_pass(ht_mesh* h, int level, int dtype, const void* kappa,
+                       const void* x, void* y, hipStream_t s) {
+  Mesh& m = h->m;
+  const CellLayout L = make_layout(level);
+  VCellArgs a{};
+  a.x = x; a.kappa = kappa; a.y = y;
+  a.kc = vcoef_couplings(h, level, dtype);
+  const auto& t = tiles_of(h, level, kVcoefJ);
+  a.tiles = t.first;
+  a.ntiles = t.second;
+  a.nblocks = m.nc * t.second;
+  a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
+  a.n = L.n;
+  {
+    Prof p(h, "cell_divkgrad", s);
+    launch_vcell(dtype, kVcoefJ, a, s);
+    check_launch();
+  }
+  ExchArgs ea = exch_args(h, level, y, nullptr, nullptr, 0.0, m.d_partials, full_range(m));
+  if (ea.total > 0) {
+    Prof p(h, "exchange", s);
+    launch_exchange(dtype, OP_APPLY, ea, s);
+    check_launch();
+  }
 }
 
 static void exch_only(ht_mesh* h, int level, int dtype, int op, void* v,
@@ -852,6 +915,8 @@ int ht_mesh_destroy(ht_mesh* h) {
       for (auto& kv : h->walk_tiles) (void)hipFree(kv.second.first);
       for (auto* p : m.d_w64) if (p) (void)hipFree(p);
       for (auto* p : m.d_w32) if (p) (void)hipFree(p);
+      for (auto* p : m.d_kc64) if (p) (void)hipFree(p);
+      for (auto* p : m.d_kc32) if (p) (void)hipFree(p);
       for (auto* list : {&m.work64, &m.work32})
         for (auto& w : *list) {
           (void)hipFree(w.u); (void)hipFree(w.b); (void)hipFree(w.t); (void)hipFree(w.d);
@@ -1061,6 +1126,18 @@ int ht_apply(ht_mesh* h, int level, int dtype, const void* x, void* y,
     check_ptr(y, "y");
     if (x == y) throw Error{HT_ERR_ARG, "x and y must not alias"};
     op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s);
+  });
+}
+
+int ht_apply_divkgrad(ht_mesh* h, int level, int dtype, const void* kappa,
+                      const void* x, void* y, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(kappa, "kappa");
+    check_ptr(x, "x");
+    check_ptr(y, "y");
+    if (y == x || y == kappa) throw Error{HT_ERR_ARG, "y must not alias x or kappa"};
+    vcoef_pass(h, level, dtype, kappa, x, y, s);
   });
 }
 

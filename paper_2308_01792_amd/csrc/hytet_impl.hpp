@@ -79,6 +79,9 @@ struct Cell {
   std::array<int32_t, 16> cls_prim; // primitive of every class (-1: interior)
   double stencil_unit[16][15];      // class partial stencils, unit scale
   double mass_unit[16];             // partial lumped masses, unit scale
+  double shape_k[6][6];             // element-matrix couplings of the six
+                                    // micro-cell shapes (vertex pairs 01 02
+                                    // 03 12 13 23), unit scale
   double volume;
 };
 
@@ -163,6 +166,8 @@ struct Mesh {
   int8_t* d_cell_order = nullptr;         // [nc][4] local index in id order
   std::vector<double*> d_w64;             // per level [nc][16][15]
   std::vector<float*> d_w32;
+  std::vector<double*> d_kc64;            // per level [nc][36] div(k grad)
+  std::vector<float*> d_kc32;             // couplings / (4 n), on first use
   double* d_partials = nullptr;           // norm partial sums
   int64_t partials_cap = 0;
   double* d_scalar = nullptr;             // reduced scalars

@@ -80,6 +80,10 @@ static void compute_cell_stencils(const double X[4][3], Cell& cell) {
       for (int r = 0; r < 4; ++r)
         K[q][r] = vol * (G[q][0] * G[r][0] + G[q][1] * G[r][1] +
                          G[q][2] * G[r][2]);
+    {
+      static const int kPairs[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+      for (int p = 0; p < 6; ++p) cell.shape_k[t][p] = K[kPairs[p][0]][kPairs[p][1]];
+    }
     // Accumulate into every boundary class: the micro-cell with the point in
     // role q is inside the closure iff none of its vertices crosses a face
     // on which the point lies (offsets have components in {-1,0,1}, so only

@@ -1,0 +1,27 @@
+// Variable-coefficient operator div(k grad) (element-wise P1 form): kernel
+// arguments and launcher shared by vcoef.hip and abi.cpp.
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <hip/hip_vector_types.h>
+
+#include "hytet_impl.hpp"
+
+namespace ht {
+
+struct VCellArgs {
+  const void* x;        // operand
+  const void* kappa;    // coefficient values at the points (consistent copies)
+  void* y;              // output: full rows inside, partial rows on the surface
+  const void* kc;       // [nc][36] level-scaled couplings (6 shapes x 6 edges)
+  const int2* tiles;    // (i0, j0) of the non-empty tiles of one cell
+  int64_t ntiles, nblocks;
+  int64_t stride, off_s0, off_s1;
+  int n;
+};
+
+// Couplings per cell: shape t, edge p (vertex pairs 01 02 03 12 13 23).
+enum { kVcoefShapes = 6, kVcoefPerCell = 36 };
+
+void launch_vcell(int dtype, int J, const VCellArgs& a, hipStream_t s);
+
+}  // namespace ht
