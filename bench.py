@@ -30,6 +30,8 @@ DIVKGRAD_BYTES_PER_DOF = {"f64": 24.0, "f32": 12.0}
 # per point: 24 micro-cells x (3-term coupling sum, 5 flops; coefficient
 # sum, 3; scaled accumulate, 2) + 14 neighbour differences
 DIVKGRAD_FLOPS_PER_DOF = 24 * 10 + 14
+# stored rows: read 15 entries and x, write y per interior DoF
+STORED_BYTES_PER_DOF = {"f64": 17 * 8.0, "f32": 17 * 4.0}
 FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
 
 
@@ -49,6 +51,7 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-divkgrad", action="store_true")
+    p.add_argument("--no-stored", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run 3 plain device copies of one level vector "
                         "(counter calibration for rocprofv3 --pmc)")
@@ -177,6 +180,43 @@ def divkgrad_leg(mesh, L, x, ndof, args, stream):
         log(f"div(k grad) apply {name}: {ms:.3f} ms/step "
             f"({res[name]['gdofs']:.1f} GDoF/s), cell kernel {cell:.3f} ms, "
             f"{gbs:.0f} GB/s, {tfl:.1f} TFLOP/s")
+        if not args.no_stored:
+            # the same operator from rows stored in the iteration order
+            y2 = torch.zeros_like(x_)
+            t0 = time.time()
+            rows = mesh.assemble_divkgrad(L, k_)
+            torch.cuda.synchronize()
+            t_asm = time.time() - t0
+            for _ in range(args.warmup):
+                mesh.apply_stored(L, rows, x_, y2)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                mesh.apply_stored(L, rows, x_, y2)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms2 = e0.elapsed_time(e1) / args.steps
+            mesh.profile(True)
+            mesh.profile_reset()
+            for _ in range(args.steps):
+                mesh.apply_stored(L, rows, x_, y2)
+            torch.cuda.synchronize()
+            sms, sn = mesh.profile_query("cell_stored")
+            mesh.profile(False)
+            diff = float((y2 - y_).abs().max()) / float(y_.abs().max())
+            gbs2 = STORED_BYTES_PER_DOF[name] * ndof / (sms / sn * 1e-3) / 1e9
+            res[name]["stored"] = {
+                "ms": round(ms2, 4), "gdofs": round(ndof / (ms2 * 1e-3) / 1e9, 3),
+                "cell_kernel_ms": round(sms / sn, 4),
+                "algorithmic_gbs": round(gbs2, 1),
+                "hbm_frac": round(gbs2 / HBM_PEAK_GBS, 4),
+                "rows_bytes": rows.numel() * rows.element_size(),
+                "assemble_seconds": round(t_asm, 3),
+                "max_rel_diff_vs_matrix_free": diff}
+            log(f"stored rows {name}: {ms2:.3f} ms/step, {gbs2:.0f} GB/s, "
+                f"rows {rows.numel() * rows.element_size() / 1e9:.1f} GB, "
+                f"rel diff vs matrix-free {diff:.1e}")
+            del rows, y2
         del k_, x_, y_
     del kap
     return res

@@ -191,6 +191,20 @@ int ht_apply(ht_mesh* mesh, int level, int dtype, const void* x, void* y,
  * call on a level.  y must not alias x or kappa. */
 int ht_apply_divkgrad(ht_mesh* mesh, int level, int dtype, const void* kappa,
                       const void* x, void* y, ht_stream stream);
+/* Stored-stencil variant of the same operator (the paper's grid-aware
+ * precomputation, Section 5.2.1): the rows are assembled once and stored in
+ * the iteration order instead of a sparse format.
+ * ht_assemble_divkgrad writes, for every slot, the 15 entries of its row of
+ * A_k (the cell's partial row at shared points) into `rows`, which holds
+ * 15 * n_slots elements of `dtype` laid out [cell][offset d][closure slot]
+ * (offset order in the documentation; entry 0 is the diagonal).
+ * ht_apply_stored computes y = A x from such rows (zero at Dirichlet
+ * micro-vertices).  Both reject levels where one cell's rows exceed 2 GiB
+ * (HT_ERR_LEVEL). */
+int ht_assemble_divkgrad(ht_mesh* mesh, int level, int dtype,
+                         const void* kappa, void* rows, ht_stream stream);
+int ht_apply_stored(ht_mesh* mesh, int level, int dtype, const void* rows,
+                    const void* x, void* y, ht_stream stream);
 /* r = b - A u (0 at Dirichlet); if norm != NULL, also ||r||_2 over unique
  * non-Dirichlet micro-vertices (synchronises the stream). */
 int ht_residual(ht_mesh* mesh, int level, int dtype, const void* u,

@@ -182,6 +182,25 @@ class Mesh:
                                        _stream()))
         return y
 
+    def assemble_divkgrad(self, level: int, kappa, rows=None):
+        """The 15 row entries of A_k per slot, [cell][offset][closure slot]
+        (15 * n_slots elements, kappa's dtype)."""
+        import torch
+        if rows is None:
+            rows = torch.empty(15 * self.n_slots(level), dtype=kappa.dtype,
+                               device=kappa.device)
+        check(load().ht_assemble_divkgrad(self._h, level, _dtype_code(kappa),
+                                          _ptr(kappa), _ptr(rows), _stream()))
+        return rows
+
+    def apply_stored(self, level: int, rows, x, y):
+        """y = A x with the rows of :meth:`assemble_divkgrad`."""
+        if rows.dtype != x.dtype or rows.numel() != 15 * self.n_slots(level):
+            raise ValueError("rows must hold 15 * n_slots entries of x's dtype")
+        check(load().ht_apply_stored(self._h, level, _dtype_code(x), _ptr(rows),
+                                     _ptr(x), _ptr(y), _stream()))
+        return y
+
     def residual(self, level: int, u, b, r, want_norm: bool = False):
         nrm = C.c_double()
         check(load().ht_residual(self._h, level, _dtype_code(u), _ptr(u),

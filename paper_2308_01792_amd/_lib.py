@@ -71,6 +71,8 @@ SIGNATURES = {
     "ht_copy": (I, [P, I, I, P, P, P]),
     "ht_apply": (I, [P, I, I, P, P, P]),
     "ht_apply_divkgrad": (I, [P, I, I, P, P, P, P]),
+    "ht_assemble_divkgrad": (I, [P, I, I, P, P, P]),
+    "ht_apply_stored": (I, [P, I, I, P, P, P, P]),
     "ht_residual": (I, [P, I, I, P, P, P, C.POINTER(D), P]),
     "ht_smooth_jacobi": (I, [P, I, I, D, I, P, P, P]),
     "ht_restrict": (I, [P, I, I, P, P, P]),

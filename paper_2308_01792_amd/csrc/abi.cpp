@@ -389,15 +389,17 @@ static const std::pair<int2*, int64_t>& tiles_of(ht_mesh* h, int level, int J) {
   return it->second;
 }
 
-// y = A_k x: cell kernel (full rows inside, partial rows on the surface),
-// then the exchange sums the partial rows (zero at Dirichlet points).
-static void vcoef_pass(ht_mesh* h, int level, int dtype, const void* kappa,
-                       const void* x, void* y, hipStream_t s) {
+// One march of the variable-coefficient kernel in `mode` over all cells;
+// VC_APPLY and VC_STORED are followed by the exchange, which sums the
+// partial rows (zero at Dirichlet points).
+static void vcoef_pass(ht_mesh* h, int level, int dtype, int mode,
+                       const void* kappa, const void* x, void* rows, void* y,
+                       hipStream_t s) {
   Mesh& m = h->m;
   const CellLayout L = make_layout(level);
   VCellArgs a{};
-  a.x = x; a.kappa = kappa; a.y = y;
-  a.kc = vcoef_couplings(h, level, dtype);
+  a.x = x; a.kappa = kappa; a.y = y; a.w = rows;
+  if (mode != VC_STORED) a.kc = vcoef_couplings(h, level, dtype);
   const auto& t = tiles_of(h, level, kVcoefJ);
   a.tiles = t.first;
   a.ntiles = t.second;
@@ -405,16 +407,23 @@ static void vcoef_pass(ht_mesh* h, int level, int dtype, const void* kappa,
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
   a.n = L.n;
   {
-    Prof p(h, "cell_divkgrad", s);
-    launch_vcell(dtype, kVcoefJ, a, s);
+    Prof p(h, mode == VC_APPLY ? "cell_divkgrad" : mode == VC_STORED ? "cell_stored" : "assemble", s);
+    launch_vcell(dtype, mode, kVcoefJ, a, s);
     check_launch();
   }
+  if (mode == VC_ASSEMBLE) return;
   ExchArgs ea = exch_args(h, level, y, nullptr, nullptr, 0.0, m.d_partials, full_range(m));
   if (ea.total > 0) {
     Prof p(h, "exchange", s);
     launch_exchange(dtype, OP_APPLY, ea, s);
     check_launch();
   }
+}
+
+// Stored rows of one cell are addressed by 32-bit byte offsets.
+static void check_stored_level(int level, int dtype) {
+  if (15 * make_layout(level).stride * (int64_t)esize(dtype) >= (int64_t)1 << 31)
+    throw Error{HT_ERR_LEVEL, "stored rows of one cell exceed 2 GiB at this level"};
 }
 
 static void exch_only(ht_mesh* h, int level, int dtype, int op, void* v,
@@ -1137,7 +1146,31 @@ int ht_apply_divkgrad(ht_mesh* h, int level, int dtype, const void* kappa,
     check_ptr(x, "x");
     check_ptr(y, "y");
     if (y == x || y == kappa) throw Error{HT_ERR_ARG, "y must not alias x or kappa"};
-    vcoef_pass(h, level, dtype, kappa, x, y, s);
+    vcoef_pass(h, level, dtype, VC_APPLY, kappa, x, nullptr, y, s);
+  });
+}
+
+int ht_assemble_divkgrad(ht_mesh* h, int level, int dtype, const void* kappa,
+                         void* rows, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(kappa, "kappa");
+    check_ptr(rows, "rows");
+    check_stored_level(level, dtype);
+    vcoef_pass(h, level, dtype, VC_ASSEMBLE, kappa, nullptr, rows, nullptr, s);
+  });
+}
+
+int ht_apply_stored(ht_mesh* h, int level, int dtype, const void* rows,
+                    const void* x, void* y, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    check_ptr(rows, "rows");
+    check_ptr(x, "x");
+    check_ptr(y, "y");
+    if (y == x) throw Error{HT_ERR_ARG, "y must not alias x"};
+    check_stored_level(level, dtype);
+    vcoef_pass(h, level, dtype, VC_STORED, nullptr, x, const_cast<void*>(rows), y, s);
   });
 }
 

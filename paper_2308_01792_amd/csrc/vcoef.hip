@@ -13,6 +13,11 @@
 // micro-cells, grouped by the faces of the cell each one would cross; on the
 // cell's surface the groups that leave the closure are dropped, which gives
 // the cell's partial row for the ghost exchange.
+//
+// The same march also serves the stored-stencil comparison (the paper's
+// grid-aware precomputation, Section 5.2.1): VC_ASSEMBLE writes each point's
+// 15 row entries (partial on the surface) in the iteration order, and
+// VC_STORED applies them, loading 15 weights per point instead of k.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -69,8 +74,10 @@ __device__ __forceinline__ void gather15(T (&v)[15], const T (&pm)[J + 2],
 
 }  // namespace
 
-template <typename T, int J>
+template <typename T, int MODE, int J>
 __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
+  constexpr bool LOAD_X = MODE != VC_ASSEMBLE;
+  constexpr bool LOAD_K = MODE != VC_STORED;
   __shared__ T ctab[kVcoefPerCell];
   // block -> (cell, tile group) in the stencil kernel's XCD-aware order
   const int64_t nb = a.nblocks;
@@ -87,9 +94,16 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
   const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
   const __amdgpu_buffer_rsrc_t rk = make_rsrc((const T*)a.kappa + cell * a.stride, bytes);
   const __amdgpu_buffer_rsrc_t ry = make_rsrc((T*)a.y + cell * a.stride, bytes);
-  if (threadIdx.x < kVcoefPerCell)
-    ctab[threadIdx.x] = ((const T*)a.kc)[cell * kVcoefPerCell + threadIdx.x];
-  __syncthreads();
+  // stored rows: 15 blocks of the cell's closure, entry d of slot s at
+  // d * stride + s
+  const __amdgpu_buffer_rsrc_t rw =
+      make_rsrc((T*)a.w + cell * 15 * a.stride, 15 * bytes);
+  const unsigned wstep = (unsigned)(a.stride * (int64_t)sizeof(T));
+  if (LOAD_K) {
+    if (threadIdx.x < kVcoefPerCell)
+      ctab[threadIdx.x] = ((const T*)a.kc)[cell * kVcoefPerCell + threadIdx.x];
+    __syncthreads();
+  }
 
   const int i = i0 - 1 + lane;
   const bool is0 = (i == 0);
@@ -126,25 +140,70 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
   };
 
   // Plane k from x planes (pm, pc, pp) and coefficient planes (qm, qc, qp)
-  // while the loads of plane k+2 go into (pn, qn).
+  // while the loads of plane k+2 go into (pn, qn); VC_STORED holds the rows
+  // of plane k in wc and loads those of plane k+1 (offsets op) into wp.
   auto step = [&](int k, T (&pm)[J + 2], T (&pc)[J + 2], T (&pp)[J + 2],
                   T (&pn)[J + 2], T (&qm)[J + 2], T (&qc)[J + 2],
                   T (&qp)[J + 2], T (&qn)[J + 2], unsigned (&oc)[J + 2],
-                  unsigned (&on)[J + 2]) {
+                  unsigned (&op)[J + 2], unsigned (&on)[J + 2],
+                  T (&wc)[J][15], T (&wp)[J][15]) {
     plane_offsets(on);
 #pragma unroll
     for (int r = 0; r < J + 2; ++r) {
-      bload(pn[r], rx, on[r]);
-      bload(qn[r], rk, on[r]);
+      if (LOAD_X) bload(pn[r], rx, on[r]);
+      if (LOAD_K) bload(qn[r], rk, on[r]);
+    }
+    if (MODE == VC_STORED) {
+#pragma unroll
+      for (int r = 0; r < J; ++r)
+#pragma unroll
+        for (int d = 0; d < 15; ++d) bload(wp[r][d], rw, op[r + 1] + (unsigned)d * wstep);
     }
 #pragma unroll
     for (int rr = 0; rr < J; ++rr) {
       const int j = j0 + rr;
       const int e = n - j - k;
       if (e < i0) continue;
-      T u[15], q[15];
-      gather15<T, J>(u, pm, pc, pp, rr);
+      const unsigned so = oc[rr + 1] | out_mask;
+      if (MODE == VC_STORED) {
+        T u[15];
+        gather15<T, J>(u, pm, pc, pp, rr);
+        T acc = wc[rr][0] * u[0];
+#pragma unroll
+        for (int d = 1; d < 15; ++d) acc = fma(wc[rr][d], u[d], acc);
+        bstore(acc, ry, so);
+        continue;
+      }
+      T q[15];
       gather15<T, J>(q, qm, qc, qp, rr);
+      // drop the micro-cells that leave the closure through a face the
+      // point lies on
+      const int cls = (int)is0 | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3);
+      if (MODE == VC_ASSEMBLE) {
+        // row entries: sum over the kept micro-cells of kbar K[q][r] at the
+        // offset of vertex r, minus their sum at the centre
+        T wd[15];
+#pragma unroll
+        for (int d = 0; d < 15; ++d) wd[d] = (T)0;
+#pragma unroll
+        for (int t = 0; t < 24; ++t) {
+          const VTet& v = kVTets[t];
+          const T ks = (q[0] + q[v.d[0]]) + (q[v.d[1]] + q[v.d[2]]);
+          const T f = (cls & v.mask) ? (T)0 : ks;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) wd[v.d[r]] = fma(f, ctab[v.p[r]], wd[v.d[r]]);
+        }
+        T centre = (T)0;
+#pragma unroll
+        for (int d = 1; d < 15; ++d) centre -= wd[d];
+        wd[0] = centre;
+#pragma unroll
+        for (int d = 0; d < 15; ++d)
+          bstore(wd[d], rw, so < HT_OOB ? so + (unsigned)d * wstep : HT_OOB);
+        continue;
+      }
+      T u[15];
+      gather15<T, J>(u, pm, pc, pp, rr);
       T du[15];
 #pragma unroll
       for (int d = 1; d < 15; ++d) du[d] = u[d] - u[0];
@@ -160,19 +219,17 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
         const T ks = (q[0] + q[v.d[0]]) + (q[v.d[1]] + q[v.d[2]]);
         g[v.mask] = fma(ks, rho, g[v.mask]);
       }
-      // drop the micro-cells that leave the closure through a face the
-      // point lies on
-      const int cls = (int)is0 | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3);
       T acc = (T)0;
 #pragma unroll
       for (int m = 1; m < 15; ++m) acc += (cls & m) ? (T)0 : g[m];
-      bstore(acc, ry, oc[rr + 1] | out_mask);
+      bstore(acc, ry, so);
     }
   };
 
   T PA[J + 2], PB[J + 2], PC[J + 2], PD[J + 2];
   T QA[J + 2], QB[J + 2], QC[J + 2], QD[J + 2];
   unsigned OA[J + 2], OB[J + 2], OC[J + 2], OD[J + 2];
+  T WA[J][15], WB[J][15];
   plane_offsets(OB);
   plane_offsets(OC);
 #pragma unroll
@@ -180,37 +237,61 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
     PA[r] = (T)0;
     QA[r] = (T)0;
     OA[r] = HT_OOB;
-    bload(PB[r], rx, OB[r]);
-    bload(QB[r], rk, OB[r]);
-    bload(PC[r], rx, OC[r]);
-    bload(QC[r], rk, OC[r]);
+    if (LOAD_X) {
+      bload(PB[r], rx, OB[r]);
+      bload(PC[r], rx, OC[r]);
+    }
+    if (LOAD_K) {
+      bload(QB[r], rk, OB[r]);
+      bload(QC[r], rk, OC[r]);
+    }
+  }
+  if (MODE == VC_STORED) {
+#pragma unroll
+    for (int r = 0; r < J; ++r)
+#pragma unroll
+      for (int d = 0; d < 15; ++d) bload(WA[r][d], rw, OB[r + 1] + (unsigned)d * wstep);
   }
   const int kmax = n - i0 - j0;
   for (int k = 0; k <= kmax; k += 4) {
-    step(k, PA, PB, PC, PD, QA, QB, QC, QD, OB, OD);
+    step(k, PA, PB, PC, PD, QA, QB, QC, QD, OB, OC, OD, WA, WB);
     if (k + 1 > kmax) break;
-    step(k + 1, PB, PC, PD, PA, QB, QC, QD, QA, OC, OA);
+    step(k + 1, PB, PC, PD, PA, QB, QC, QD, QA, OC, OD, OA, WB, WA);
     if (k + 2 > kmax) break;
-    step(k + 2, PC, PD, PA, PB, QC, QD, QA, QB, OD, OB);
+    step(k + 2, PC, PD, PA, PB, QC, QD, QA, QB, OD, OA, OB, WA, WB);
     if (k + 3 > kmax) break;
-    step(k + 3, PD, PA, PB, PC, QD, QA, QB, QC, OA, OC);
+    step(k + 3, PD, PA, PB, PC, QD, QA, QB, QC, OA, OB, OC, WB, WA);
   }
 }
 
-template <typename T>
+template <typename T, int MODE>
 static void launch_vcell_t(int J, const VCellArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)(((a.nblocks + 7) / 8) * 8)), block(64 * kCellWaves);
   switch (J) {
-    case 2: hipLaunchKernelGGL((k_vcell<T, 2>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_vcell<T, 4>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_vcell<T, MODE, 2>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_vcell<T, MODE, 4>), grid, block, 0, s, a); break;
     default: throw Error{HT_ERR_ARG, "variable-coefficient tile rows must be 2 or 4"};
   }
 }
 
-void launch_vcell(int dtype, int J, const VCellArgs& a, hipStream_t s) {
+template <typename T>
+static void launch_vcell_mode(int mode, int J, const VCellArgs& a, hipStream_t s) {
+  switch (mode) {
+    case VC_APPLY: launch_vcell_t<T, VC_APPLY>(J, a, s); break;
+    case VC_ASSEMBLE: launch_vcell_t<T, VC_ASSEMBLE>(J, a, s); break;
+    case VC_STORED: launch_vcell_t<T, VC_STORED>(J, a, s); break;
+    default: throw Error{HT_ERR_ARG, "unknown variable-coefficient kernel mode"};
+  }
+}
+
+void launch_vcell(int dtype, int mode, int J, const VCellArgs& a, hipStream_t s) {
   if (a.nblocks <= 0) return;
-  if (dtype == HT_F64) launch_vcell_t<double>(J, a, s);
-  else launch_vcell_t<float>(J, a, s);
+  if ((mode == VC_APPLY || mode == VC_ASSEMBLE) && (!a.kappa || !a.kc))
+    throw Error{HT_ERR_ARG, "div(k grad) kernel needs k and the couplings"};
+  if ((mode == VC_ASSEMBLE || mode == VC_STORED) && !a.w)
+    throw Error{HT_ERR_ARG, "stored-stencil kernel needs the row array"};
+  if (dtype == HT_F64) launch_vcell_mode<double>(mode, J, a, s);
+  else launch_vcell_mode<float>(mode, J, a, s);
 }
 
 }  // namespace ht

@@ -13,6 +13,7 @@ struct VCellArgs {
   const void* kappa;    // coefficient values at the points (consistent copies)
   void* y;              // output: full rows inside, partial rows on the surface
   const void* kc;       // [nc][36] level-scaled couplings (6 shapes x 6 edges)
+  void* w;              // stored rows [nc][15][stride] (assemble / stored apply)
   const int2* tiles;    // (i0, j0) of the non-empty tiles of one cell
   int64_t ntiles, nblocks;
   int64_t stride, off_s0, off_s1;
@@ -22,6 +23,10 @@ struct VCellArgs {
 // Couplings per cell: shape t, edge p (vertex pairs 01 02 03 12 13 23).
 enum { kVcoefShapes = 6, kVcoefPerCell = 36 };
 
-void launch_vcell(int dtype, int J, const VCellArgs& a, hipStream_t s);
+// VC_APPLY: y = A_k x matrix-free; VC_ASSEMBLE: write the 15 row entries of
+// A_k per point into w (x unused); VC_STORED: y = A x with the rows in w.
+enum { VC_APPLY = 0, VC_ASSEMBLE = 1, VC_STORED = 2 };
+
+void launch_vcell(int dtype, int mode, int J, const VCellArgs& a, hipStream_t s);
 
 }  // namespace ht

@@ -103,3 +103,77 @@ def test_divkgrad_is_deterministic():
     P.m.apply_divkgrad(3, k, x, y1)
     P.m.apply_divkgrad(3, k, x, y2)
     assert torch.equal(y1, y2)
+
+
+# ------------------------------------------------ stored-stencil variant --
+@pytest.mark.parametrize("name,level", [("ref_tet", 4), ("jittered_288", 3),
+                                        ("kuhn_211", 3), ("slab_3_11", 3)])
+def test_stored_rows_apply_matches_oracle(name, level):
+    P = pair(name, level)
+    mesh = P.S(level).mesh
+    kv = fields.coefficient_field(mesh.xyz)
+    S = P1System(mesh, kappa=kv)
+    x = fields.uniform_values(mesh.num_vertices, 17)
+    kg, xg = P.to_gpu(level, kv), P.to_gpu(level, x)
+    rows = P.m.assemble_divkgrad(level, kg)
+    yg = torch.full_like(xg, np.nan)
+    P.m.apply_stored(level, rows, xg, yg)
+    torch.cuda.synchronize()
+    y = P.from_gpu(level, yg)
+    assert rel_err(y, S.apply(x)) <= FP64_TOL
+
+
+def test_stored_rows_are_the_matrix_rows():
+    """At points inside one macro-cell the 15 stored entries are the
+    oracle's matrix entries a(v, v + d) (the diagonal at d = 0)."""
+    from oracle.refine import keys_of
+    level = 3
+    P = pair("jittered_288", level)
+    mesh = P.S(level).mesh
+    kv = fields.coefficient_field(mesh.xyz)
+    A = P1System(mesh, kappa=kv).A.tocsr()
+    rows = P.m.assemble_divkgrad(level, P.to_gpu(level, kv)).cpu().numpy()
+    nslot = P.m.n_slots(level)
+    stride = nslot // len(mesh.cells)
+    offs = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0),
+            (0, 0, 1), (0, 0, -1), (-1, 1, 0), (1, -1, 0), (-1, 0, 1),
+            (1, 0, -1), (0, -1, 1), (0, 1, -1), (1, -1, 1), (-1, 1, -1)]
+    n = 2 ** level
+
+    def vertex(c, i, j, k):
+        w = np.array([[n - i - j - k, i, j, k]], dtype=np.int64)
+        return int(mesh.index_of(keys_of(mesh.cells[c], w))[0])
+
+    checked = 0
+    for c in (0, 17, 200):
+        for (i, j, k) in [(1, 1, 1), (2, 3, 1), (1, 2, 4), (3, 2, 2)]:
+            s = P.m.slot_index(level, c, i, j, k)
+            local = s - c * stride
+            v = vertex(c, i, j, k)
+            for d, (di, dj, dk) in enumerate(offs):
+                w = vertex(c, i + di, j + dj, k + dk)
+                got = rows[c * 15 * stride + d * stride + local]
+                assert abs(got - A[v, w]) <= 1e-13 * abs(A[v, v]), (c, i, j, k, d)
+            checked += 1
+    assert checked == 12
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13),
+                                       (torch.float32, 3e-5)])
+def test_stored_equals_matrix_free(dtype, tol):
+    P = pair("jittered_288", 4)
+    mesh = P.S(4).mesh
+    kg = P.to_gpu(4, fields.coefficient_field(mesh.xyz), dtype)
+    xg = P.to_gpu(4, fields.uniform_values(mesh.num_vertices, 18), dtype)
+    y1, y2 = torch.zeros_like(xg), torch.zeros_like(xg)
+    P.m.apply_divkgrad(4, kg, xg, y1)
+    P.m.apply_stored(4, P.m.assemble_divkgrad(4, kg), xg, y2)
+    scale = float(y1.abs().max())
+    assert float((y1 - y2).abs().max()) <= tol * scale
+
+
+def test_stored_rejects_wrong_row_count():
+    P = pair("ref_tet", 2)
+    x = torch.zeros(P.m.n_slots(2), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        P.m.apply_stored(2, x, x, torch.zeros_like(x))
