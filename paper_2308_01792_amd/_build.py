@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhytet.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mesh.cpp", "abi.cpp", "kernels.hip", "vcoef.hip"]
+SOURCES = ["mesh.cpp", "abi.cpp", "kernels.hip", "walk.hip", "vcoef.hip"]
 ARCH = os.environ.get("HYTET_ARCH", "gfx950")
 
 

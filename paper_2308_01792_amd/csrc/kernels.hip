@@ -483,253 +483,6 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
   }
 }
 
-// --------------------------------------------------------- tile walker --
-// The transfer and elementwise kernels visit the closure points of one
-// (cell, walk tile) per wave: lanes are 64 consecutive i = i0 + lane, rows
-// j0 .. j0 + kWalkRows - 1, planes k = 0 .. n - i0 - j0.  A workgroup holds
-// kWalkWaves waves on consecutive walk tiles, so that enough waves are
-// resident per CU for these streaming kernels.
-enum { kWalkRows = 8, kWalkWaves = 4 };
-
-// (block, wave) -> (cell, tile).  Consecutive blocks go to different XCDs;
-// each XCD gets one contiguous run of tiles, as in the stencil kernel.
-__device__ __forceinline__ bool walk_block(int64_t nblocks, int64_t ntiles,
-                                           const int2* tiles, int wave,
-                                           int64_t& cell, int& i0, int& j0,
-                                           int64_t& w) {
-  const int64_t groups = (nblocks + kWalkWaves - 1) / kWalkWaves;
-  const int64_t chunk = (groups + 7) / 8;
-  w = ((int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8) * kWalkWaves + wave;
-  if (w >= nblocks) return false;
-  cell = w / ntiles;
-  const int2 t = tiles[w % ntiles];
-  i0 = t.x;
-  j0 = t.y;
-  return true;
-}
-
-// Prolongation u_f += P e_c, fine walk: a fine point with even index copies
-// the coarse value at half its index; otherwise it is the midpoint of the
-// coarse micro-edge along the one direction d with the same parity, and
-// takes the mean of the coarse values at (f - d)/2 and (f + d)/2 (for even
-// points both parents coincide and the mean is exact).  Coarse Dirichlet
-// values count as zero.  The coarse rows of the parents only depend on the
-// lane parity, so their bases are computed once per row (scalar).
-struct CRow {
-  int mb, sa, sb, e;
-};
-__device__ __forceinline__ CRow crow(const Lay& L, int j, int k) {
-  const int n = L.n;
-  CRow r;
-  r.e = n - j - k;
-  r.mb = (int)tw32(n - 1, 0, j, k) - 1;
-  r.sa = (int)L.off_s0 + (int)t2w32(n + 1, j, k);
-  r.sb = (int)L.off_s1 + (int)t2w32(n, j, k);
-  return r;
-}
-__device__ __forceinline__ void parity_dir(int p, int& di, int& dj, int& dk) {
-  // direction with parity p among x, y, xy, z, xz, yz, xyz (0 for p = 0)
-  di = (p == 1 || p == 7) ? 1 : ((p == 3 || p == 5) ? -1 : 0);
-  dj = (p == 2 || p == 3) ? 1 : ((p == 6 || p == 7) ? -1 : 0);
-  dk = (p >= 4) ? 1 : 0;
-}
-
-template <typename T>
-__global__ __launch_bounds__(64 * kWalkWaves) void k_prolong(XferArgs a) {
-  int64_t cell, w;
-  int i0, j0;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if (!walk_block(a.nblocks, a.ntiles, a.tiles, wave, cell, i0, j0, w)) return;
-  const int lane = threadIdx.x & 63;
-  const uint8_t fl = lane < 16 ? a.cls[cell * 16 + lane].flags : 0;
-  const unsigned dmask = (unsigned)__ballot((fl & kClsDirichlet) != 0) & 0xffffu;
-  const Lay Lf{a.nf, a.stride_f, a.off_s0_f, a.off_s1_f};
-  const Lay Lc{a.nc_, a.stride_c, a.off_s0_c, a.off_s1_c};
-  const __amdgpu_buffer_rsrc_t rc =
-      make_rsrc((const T*)a.src + cell * Lc.stride, Lc.stride * (int64_t)sizeof(T));
-  const __amdgpu_buffer_rsrc_t ru =
-      make_rsrc((T*)a.dst + cell * Lf.stride, Lf.stride * (int64_t)sizeof(T));
-  const int n = Lf.n, w1 = n - 1, i = i0 + lane;
-  const bool odd = (i & 1) != 0;
-  const int kmax = n - i0 - j0;
-  for (int k = 0; k <= kmax; ++k) {
-    // all loads of the plane's rows first, then the updates
-    unsigned ou[kWalkRows], oa[kWalkRows], ob[kWalkRows];
-    bool za[kWalkRows], zb[kWalkRows];
-    int mb = (int)(tet32(w1) - tet32(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
-    int sa = (int)Lf.off_s0 + (int)(tri32(n + 1) - tri32(n + 1 - k)) + j0;
-    int sb = (int)Lf.off_s1 + (int)(tri32(n) - tri32(n - k)) + j0;
-#pragma unroll
-    for (int r = 0; r < kWalkRows; ++r) {
-      const int j = j0 + r;
-      const int e = n - j - k;
-      const bool valid = e >= i0 && i <= e;
-      const int el = i == 0 ? sa : (i == e ? sb : mb + i);
-      ou[r] = valid ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB;
-      mb += w1 - k - j;
-      ++sa;
-      ++sb;
-      // parents: uniform coarse rows for even and odd lanes
-      const int pj = j & 1, pk = k & 1;
-      const int q0 = (pj << 1) | (pk << 2), q1 = q0 | 1;
-      int di0, dj0, dk0, di1, dj1, dk1;
-      parity_dir(q0, di0, dj0, dk0);
-      parity_dir(q1, di1, dj1, dk1);
-      const int di = odd ? di1 : di0;
-      auto parent = [&](int sgn, unsigned& off, bool& zero) {
-        const int jr0 = (j + sgn * dj0) >> 1, kr0 = (k + sgn * dk0) >> 1;
-        const int jr1 = (j + sgn * dj1) >> 1, kr1 = (k + sgn * dk1) >> 1;
-        const CRow R0 = crow(Lc, jr0, kr0), R1 = crow(Lc, jr1, kr1);
-        const int mbc = odd ? R1.mb : R0.mb, sac = odd ? R1.sa : R0.sa;
-        const int sbc = odd ? R1.sb : R0.sb, ec = odd ? R1.e : R0.e;
-        const int jr = odd ? jr1 : jr0, kr = odd ? kr1 : kr0;
-        const int ic = (i + sgn * di) >> 1;
-        int e2 = (ic == ec) ? sbc : mbc + ic;
-        e2 = (ic == 0) ? sac : e2;
-        const int cls = (ic == 0) | ((jr == 0) << 1) | ((kr == 0) << 2) | ((ic == ec) << 3);
-        off = valid ? (unsigned)e2 * (unsigned)sizeof(T) : HT_OOB;
-        zero = ((dmask >> cls) & 1u) != 0;
-      };
-      parent(-1, oa[r], za[r]);
-      parent(+1, ob[r], zb[r]);
-    }
-    T u[kWalkRows], va[kWalkRows], vb[kWalkRows];
-#pragma unroll
-    for (int r = 0; r < kWalkRows; ++r) {
-      bload(u[r], ru, ou[r]);
-      bload(va[r], rc, oa[r]);
-      bload(vb[r], rc, ob[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < kWalkRows; ++r) {
-      const T x = za[r] ? (T)0 : va[r];
-      const T y = zb[r] ? (T)0 : vb[r];
-      bstore(u[r] + (T)0.5 * (x + y), ru, ou[r]);
-    }
-  }
-}
-
-// Elementwise kernels over the closure points.  Per plane, the offsets of
-// all rows of the tile are formed first and every load is issued before any
-// result is used.
-template <typename T, int EOP>
-__global__ __launch_bounds__(64 * kWalkWaves) void k_elem(ElemArgs a) {
-  int64_t cell, w;
-  int i0, j0;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
-  const bool live = walk_block(a.nblocks, a.ntiles, a.tiles, wave, cell, i0, j0, w);
-  // class table of the wave's cell; every wave reaches the barrier
-  __shared__ ClassInfo cis[kWalkWaves][16];
-  if (live && lane < 16) cis[wave][lane] = a.cls[cell * 16 + lane];
-  __syncthreads();
-  if (!live) return;
-  const ClassInfo* ci = cis[wave];
-  const Lay L{a.n, a.stride, a.off_s0, a.off_s1};
-  const int64_t cb = cell * L.stride;
-  const int64_t bytes = L.stride * (int64_t)sizeof(T);
-  const __amdgpu_buffer_rsrc_t r0 =
-      make_rsrc(a.in0 ? (const T*)a.in0 + cb : (const T*)a.out + cb, bytes);
-  const __amdgpu_buffer_rsrc_t r1 =
-      make_rsrc(a.in1 ? (const T*)a.in1 + cb : (const T*)a.out + cb, bytes);
-  const __amdgpu_buffer_rsrc_t ro = make_rsrc((T*)a.out + cb, bytes);
-  const int n = L.n, w1 = n - 1, i = i0 + lane;
-  const int kmax = n - i0 - j0;
-  double acc = 0.0;
-  for (int k = 0; k <= kmax; ++k) {
-    unsigned off[kWalkRows];
-    int cl[kWalkRows], elr[kWalkRows];
-    int mb = (int)(tet32(w1) - tet32(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
-    int sa = (int)L.off_s0 + (int)(tri32(n + 1) - tri32(n + 1 - k)) + j0;
-    int sb = (int)L.off_s1 + (int)(tri32(n) - tri32(n - k)) + j0;
-#pragma unroll
-    for (int r = 0; r < kWalkRows; ++r) {
-      const int j = j0 + r;
-      const int e = n - j - k;
-      const bool valid = e >= i0 && i <= e;
-      elr[r] = i == 0 ? sa : (i == e ? sb : mb + i);
-      off[r] = valid ? (unsigned)elr[r] * (unsigned)sizeof(T) : HT_OOB;
-      cl[r] = valid ? ((i == 0) | ((j == 0) << 1) | ((k == 0) << 2) | ((i == e) << 3)) : -1;
-      mb += w1 - k - j;
-      ++sa;
-      ++sb;
-    }
-    if (EOP == EOP_ZERO_GUESS) {
-      // first Jacobi sweep from u = 0: u = omega D^-1 b
-      T bv[kWalkRows];
-#pragma unroll
-      for (int r = 0; r < kWalkRows; ++r) bload(bv[r], r0, off[r]);
-#pragma unroll
-      for (int r = 0; r < kWalkRows; ++r) {
-        const ClassInfo& c = ci[cl[r] < 0 ? 0 : cl[r]];
-        const T f = (c.flags & kClsDirichlet) ? (T)0 : (T)(a.alpha * a.nscale * c.inv_diag_unit);
-        bstore(f * bv[r], ro, off[r]);
-      }
-    } else if (EOP == EOP_DOT) {
-      T xv[kWalkRows], yv[kWalkRows];
-#pragma unroll
-      for (int r = 0; r < kWalkRows; ++r) {
-        bload(xv[r], r0, off[r]);
-        bload(yv[r], r1, off[r]);
-      }
-#pragma unroll
-      for (int r = 0; r < kWalkRows; ++r) {
-        const uint8_t f = cl[r] < 0 ? 0 : ci[cl[r]].flags;
-        const bool use = (f & kClsOwner) && !(f & kClsDirichlet);
-        acc += use ? (double)xv[r] * (double)yv[r] : 0.0;
-      }
-    } else if (EOP == EOP_MASS) {
-#pragma unroll
-      for (int r = 0; r < kWalkRows; ++r)
-        bstore((T)(ci[cl[r] < 0 ? 0 : cl[r]].mass_unit * a.nscale), ro, off[r]);
-    } else if (EOP == EOP_ZERO_INTERIOR) {
-#pragma unroll
-      for (int r = 0; r < kWalkRows; ++r) {
-        const bool dir = cl[r] >= 0 && (ci[cl[r]].flags & kClsDirichlet);
-        bstore((T)0, ro, dir ? HT_OOB : off[r]);
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < kWalkRows; ++r) {
-        if (cl[r] < 0) continue;
-        const ClassInfo& c = ci[cl[r]];
-        const int64_t s = cb + elr[r];
-        if (EOP == EOP_FLAGS) {
-          uint8_t f = (c.flags & kClsOwner) ? HT_SLOT_OWNER : HT_SLOT_GHOST;
-          if (c.flags & kClsDirichlet) f |= HT_SLOT_DIRICHLET;
-          ((uint8_t*)a.out)[s] = f;
-        } else if (EOP == EOP_COORDS || EOP == EOP_PROBE) {
-          const double* X = a.cell_xyz + cell * 12;     // sorted by global id
-          const int8_t* ord = a.cell_order + cell * 4;  // local index per sorted
-          const int j = j0 + r;
-          const int wl[4] = {n - i - j - k, i, j, k};
-          T* o = (T*)a.out;
-          double xyz[3];
-          for (int a3 = 0; a3 < 3; ++a3) {
-            double sum = 0.0;
-            for (int q = 0; q < 4; ++q) {
-              const int wq = wl[ord[q]];
-              if (wq > 0) sum += (double)wq * X[3 * q + a3];
-            }
-            xyz[a3] = sum * a.alpha;
-            if (EOP == EOP_COORDS) o[3 * s + a3] = (T)xyz[a3];
-          }
-          if (EOP == EOP_PROBE) {
-            // start vector of the power iteration: a field that oscillates
-            // on the scale of the finest micro-cells, zero on the boundary
-            const double ph = 1000.0 * xyz[0] + 1700.0 * xyz[1] + 2300.0 * xyz[2];
-            o[s] = (c.flags & kClsDirichlet) ? (T)0 : (T)sin(ph);
-          }
-        }
-      }
-    }
-  }
-  if (EOP == EOP_DOT) {
-    acc = wave_sum(acc);
-    if (lane == 0) a.partials[w] = acc;
-  }
-}
-
 // Flat elementwise kernels over all slots (padding included).
 template <typename TO, typename TI, int FOP>
 __global__ __launch_bounds__(256) void k_flat(FlatArgs a) {
@@ -862,35 +615,6 @@ void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
     throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input and y32"};
   if (dtype == HT_F64) launch_exchange_t<double>(op, a, s);
   else launch_exchange_t<float>(op, a, s);
-}
-
-static dim3 walk_grid(int64_t nblocks) {
-  const int64_t groups = (nblocks + kWalkWaves - 1) / kWalkWaves;
-  return dim3((unsigned)(((groups + 7) / 8) * 8));
-}
-
-void launch_prolong(int dtype, const XferArgs& a, hipStream_t s) {
-  const dim3 grid = walk_grid(a.nblocks), block(64 * kWalkWaves);
-  if (dtype == HT_F64) hipLaunchKernelGGL(k_prolong<double>, grid, block, 0, s, a);
-  else hipLaunchKernelGGL(k_prolong<float>, grid, block, 0, s, a);
-}
-
-template <typename T>
-static void launch_elem_t(int eop, const ElemArgs& a, hipStream_t s) {
-  const dim3 grid = walk_grid(a.nblocks), block(64 * kWalkWaves);
-  switch (eop) {
-    case EOP_ZERO_GUESS: hipLaunchKernelGGL((k_elem<T, EOP_ZERO_GUESS>), grid, block, 0, s, a); break;
-    case EOP_MASS: hipLaunchKernelGGL((k_elem<T, EOP_MASS>), grid, block, 0, s, a); break;
-    case EOP_ZERO_INTERIOR: hipLaunchKernelGGL((k_elem<T, EOP_ZERO_INTERIOR>), grid, block, 0, s, a); break;
-    case EOP_DOT: hipLaunchKernelGGL((k_elem<T, EOP_DOT>), grid, block, 0, s, a); break;
-    case EOP_FLAGS: hipLaunchKernelGGL((k_elem<T, EOP_FLAGS>), grid, block, 0, s, a); break;
-    case EOP_COORDS: hipLaunchKernelGGL((k_elem<T, EOP_COORDS>), grid, block, 0, s, a); break;
-    case EOP_PROBE: hipLaunchKernelGGL((k_elem<T, EOP_PROBE>), grid, block, 0, s, a); break;
-  }
-}
-void launch_elem(int dtype, int eop, const ElemArgs& a, hipStream_t s) {
-  if (dtype == HT_F64) launch_elem_t<double>(eop, a, s);
-  else launch_elem_t<float>(eop, a, s);
 }
 
 void launch_flat(int dto, int dti, int fop, const FlatArgs& a, hipStream_t s) {
