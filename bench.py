@@ -253,8 +253,8 @@ def cpu_baseline(level: int, budget_s: float):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU "
-              "path (see DESIGN.md, 'Sharding'); run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU "
+              "path (the design notes describe how it would shard); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import torch

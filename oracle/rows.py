@@ -7,12 +7,16 @@ matrix of T (Section 5.2.1).  Those micro-tets are found by descending the
 refinement tree of eq. (bey) in every macro-cell whose closure holds p: at each
 level only the children whose closed simplex contains p are refined further,
 so the work is (number of tets around p) x 8 x level.
+
+With a coefficient k (the div(k grad) form of fem.py), each element matrix
+is scaled by the degree-3 rule applied to k's values at the micro-tet's
+vertices, as in the assembly.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .fem import element_stiffness
+from .fem import element_coefficient_mean, element_stiffness
 from .refine import key_coordinates, keys_of, refine_once
 
 
@@ -48,8 +52,11 @@ def local_tets(cell_ids: np.ndarray, n_level: int, level: int,
 
 
 def row_at(macro_xyz: np.ndarray, cells: np.ndarray, level: int,
-           key: np.ndarray):
+           key: np.ndarray, kappa=None):
     """Row of the P1 stiffness matrix at the keyed micro-vertex.
+
+    ``kappa``, if given, maps micro-vertex keys [m, 4, 8] to the values of
+    the coefficient k there [m, 4]; the row is then that of div(k grad).
 
     Returns (neighbour keys [r, 8], values [r], is_dirichlet).  The point is a
     Dirichlet vertex when one of the micro-faces through it belongs to a
@@ -67,6 +74,8 @@ def row_at(macro_xyz: np.ndarray, cells: np.ndarray, level: int,
         tkeys = keys_of(np.asarray(cells[c]), tets)          # [m, 4, 8]
         P = key_coordinates(macro_xyz, tkeys, n)             # [m, 4, 3]
         K, _ = element_stiffness(P)
+        if kappa is not None:
+            K = K * element_coefficient_mean(kappa(tkeys))[:, None, None]
         for t in range(len(tets)):
             vk = [tuple(tkeys[t, q]) for q in range(4)]
             q0 = vk.index(tuple(key))

@@ -105,8 +105,8 @@ def test_norm_and_dot_count_unique_interior_dofs():
 
 
 @pytest.mark.parametrize("run", [1, 2])
-def test_c1_jacobi_ten_sweeps(run):
-    """C1: reference tet, level 4, omega = 2/3, ten sweeps.  Run 1: b = 0,
+def test_ref_tet_jacobi_ten_sweeps(run):
+    """Reference tet, level 4, omega = 2/3, ten sweeps.  Run 1: b = 0,
     u0 ~ U[-1,1] (seed 0) with zero boundary; run 2: b ~ U[-1,1] (seed 1),
     u0 = 0."""
     P = pair("ref_tet", 4, 4)

@@ -81,9 +81,9 @@ def test_mesh_errors(lib):
     assert e.value.code == _lib.HT_ERR_MESH
     # three cells on one face
     X = np.vstack([xyz, [[0.3, 0.3, -1.0], [0.2, 0.2, 0.5]]])
-    C3 = np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]])
+    three = np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]])
     with pytest.raises(ht.HytetError) as e:
-        ht.Mesh(X, C3, 0, 2)
+        ht.Mesh(X, three, 0, 2)
     assert e.value.code == _lib.HT_ERR_MESH
     m = ht.Mesh(xyz, cells, 1, 3)
     with pytest.raises(ht.HytetError) as e:
@@ -166,12 +166,12 @@ def test_class_stencils_assemble_to_oracle_matrix(lib, name, level):
 def test_interior_stencil_closed_form_reference_tet(lib):
     """Class-0 stencil of the reference tet at level 4 equals the closed form
     (centre 20/(3n), axis x,z -4/(3n), ...), in the library's offset order."""
-    from tests.test_oracle_pins import C1_STENCIL
+    from tests.test_oracle_pins import REF_TET_STENCIL
     m = ht.Mesh(*mesh_by_name("ref_tet"), 4, 4)
     W = m.cell_stencils(4)[0, 0]
     n = 16
     for d, off in enumerate(OFFSETS):
-        assert W[d] == pytest.approx(C1_STENCIL[off] / (3 * n), abs=1e-15)
+        assert W[d] == pytest.approx(REF_TET_STENCIL[off] / (3 * n), abs=1e-15)
 
 
 def test_level_scaling_is_exact(lib):

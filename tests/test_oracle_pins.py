@@ -51,7 +51,7 @@ def test_counts_single_cell(level):
     assert m.num_vertices == N_tet(n + 1) == (n + 1) * (n + 2) * (n + 3) // 6
     assert len(m.tets) == 8 ** level
     if level == 4:
-        assert m.num_vertices == 969          # C1: 969 micro-vertices
+        assert m.num_vertices == 969          # reference tet, level 4: 969 micro-vertices
 
 
 @pytest.mark.parametrize("shape,level", [((1, 1, 1), 3), ((2, 1, 1), 2),
@@ -165,10 +165,10 @@ def test_child_vertices_follow_eq_bey():
 
 
 # --------------------------------------------------------- closed forms --
-# C1 interior stencil (reference tet, every cell-interior point), in units of
-# 1/(3n): offsets (di, dj, dk) -> weight.  Derived from the six Bey micro-cell
-# shapes; see DESIGN.md "closed-form stencils".
-C1_STENCIL = {(0, 0, 0): 20, (1, 0, 0): -4, (-1, 0, 0): -4, (0, 0, 1): -4,
+# Interior stencil of the reference tet (every cell-interior point), in units of
+# 1/(3n): offsets (di, dj, dk) -> weight.  Derived by hand from the element
+# matrices of the six Bey micro-cell shapes of the reference cell.
+REF_TET_STENCIL = {(0, 0, 0): 20, (1, 0, 0): -4, (-1, 0, 0): -4, (0, 0, 1): -4,
               (0, 0, -1): -4, (0, 1, 0): -2, (0, -1, 0): -2, (-1, 1, 0): -1,
               (1, -1, 0): -1, (0, -1, 1): -1, (0, 1, -1): -1, (-1, 0, 1): 1,
               (1, 0, -1): 1, (1, -1, 1): 1, (-1, 1, -1): 1}
@@ -189,8 +189,8 @@ def test_reference_tet_interior_rows_closed_form(level):
             d = tuple(idx[A.indices[p]] - idx[v])
             row[d] = A.data[p] * 3 * n
         row = {d: w for d, w in row.items() if abs(w) > 1e-12}
-        assert set(row) == set(C1_STENCIL)
-        for d, w in C1_STENCIL.items():
+        assert set(row) == set(REF_TET_STENCIL)
+        for d, w in REF_TET_STENCIL.items():
             assert abs(row[d] - w) < 1e-11, (d, row[d], w)
     # the seven direction classes are all present with their neighbours
     assert where[(1, 1, 1)] >= 0
@@ -383,8 +383,8 @@ def test_vcycle_converges_to_direct_solution():
     assert np.abs(u[I] - ud).max() <= 1e-8 * np.abs(ud).max()
 
 
-# --------------------------------------------- manufactured Poisson (C2) --
-def _c2_errors(levels):
+# ---------------------------------- manufactured Poisson, unit cube --
+def _cube_errors(levels):
     out = []
     for lvl in levels:
         S = P1System(MicroMesh(*mesh_by_name("kuhn_cube"), lvl))
@@ -395,28 +395,28 @@ def _c2_errors(levels):
     return out
 
 
-def test_c2_exact_discrete_solution():
+def test_unit_cube_exact_discrete_solution():
     """Kuhn cube + lumped right-hand side = the 7-point scheme, whose discrete
     solution for f = 3 pi^2 sin sin sin is c_h u(x_i) exactly, with
     c_h = (pi h / 2)^2 / sin^2(pi h / 2)."""
-    for S, I, uh in _c2_errors([3, 4, 5]):
+    for S, I, uh in _cube_errors([3, 4, 5]):
         h = 1.0 / S.mesh.n
         ch = (np.pi * h / 2) ** 2 / np.sin(np.pi * h / 2) ** 2
         exact = ch * fields.sine_solution(S.mesh.xyz[I])
         assert np.abs(uh - exact).max() <= 1e-10
 
 
-def test_c2_second_order_convergence():
+def test_unit_cube_second_order_convergence():
     """Max nodal error ratios between consecutive levels approach 4 (O(h^2),
     the rate the paper shows for its own convergence study)."""
     errs = [np.abs(uh - fields.sine_solution(S.mesh.xyz[I])).max()
-            for S, I, uh in _c2_errors([2, 3, 4, 5])]
+            for S, I, uh in _cube_errors([2, 3, 4, 5])]
     ratios = np.array(errs[:-1]) / np.array(errs[1:])
     assert ((ratios > 3.8) & (ratios < 4.2)).all(), ratios
 
 
 # ------------------------------------------------ full multigrid (FMG) --
-def _c2_problem(H, lvl):
+def _cube_problem(H, lvl):
     """Lumped sine right-hand side on the unit cube and its exact discrete
     solution c_h u(x) (the 7-point scheme's eigenfunction)."""
     S = H[lvl]
@@ -433,7 +433,7 @@ def test_fmg_converges_to_the_discrete_solution():
     """Many cycles per level: nested iteration ends at the exact discrete
     solution, known in closed form."""
     H = oracle_hierarchy("kuhn_cube", 4, 2)
-    S, b, uh, disc = _c2_problem(H, 4)
+    S, b, uh, disc = _cube_problem(H, 4)
     u = H.fmg(4, b, cycles=30, coarse_level=2)
     assert np.abs(u - uh)[S.interior].max() <= 1e-9 * disc
 
@@ -444,7 +444,7 @@ def test_fmg_reaches_the_discretisation_error():
     iteration: the error does not accumulate across levels)."""
     H = oracle_hierarchy("kuhn_cube", 5, 2)
     for lvl in (3, 4, 5):
-        S, b, uh, disc = _c2_problem(H, lvl)
+        S, b, uh, disc = _cube_problem(H, lvl)
         u = H.fmg(lvl, b, cycles=5, coarse_level=2)
         assert np.abs(u - uh)[S.interior].max() <= 0.25 * disc
 
@@ -527,11 +527,11 @@ def test_vcycle_with_chebyshev_smoother_converges():
     assert rates.max() < 0.35 and hist[-1] <= 1e-7 * hist[0]
 
 
-# ----------------------------------- second, lattice-based oracle for C1 --
-def test_c1_lattice_stencil_reproduces_oracle():
+# -------------------------- second, lattice-based oracle, reference tet --
+def test_ref_tet_lattice_stencil_reproduces_oracle():
     """A separate lattice code (closed-form stencil on the index grid of the
     reference tet, no assembly) reproduces the oracle's apply and ten Jacobi
-    sweeps (omega = 2/3) on C1 (level 4, u ~ U[-1,1], zero boundary)."""
+    sweeps (omega = 2/3) on the reference tet (level 4, u ~ U[-1,1], zero boundary)."""
     level, n = 4, 16
     S = P1System(MicroMesh(*mesh_by_name("ref_tet"), level))
     idx = local_index(S.mesh)
@@ -545,7 +545,7 @@ def test_c1_lattice_stencil_reproduces_oracle():
         grid[:] = 0.0
         grid[idx[:, 0] + 1, idx[:, 1] + 1, idx[:, 2] + 1] = vals
         out = np.zeros_like(vals)
-        for d, w in C1_STENCIL.items():
+        for d, w in REF_TET_STENCIL.items():
             out += w / (3 * n) * grid[idx[:, 0] + 1 + d[0], idx[:, 1] + 1 + d[1],
                                       idx[:, 2] + 1 + d[2]]
         return np.where(inner, out, 0.0)
@@ -631,3 +631,22 @@ def test_coefficient_energy_identity():
     assert np.abs(A @ np.ones(A.shape[0])).max() <= 1e-13 * abs(A).max()
     AII, _ = S.interior_matrix()
     np.linalg.cholesky(AII.toarray())
+
+
+def test_row_oracle_with_coefficient_matches_assembly():
+    """Single rows of div(k grad), k looked up by key, against the assembled
+    matrix of the same coefficient values."""
+    mesh = MicroMesh(*mesh_by_name("jittered_288"), 3)
+    kv = fields.coefficient_field(mesh.xyz)
+    S = P1System(mesh, kappa=kv)
+
+    def kappa(tkeys):
+        return kv[mesh.index_of(tkeys)]
+
+    rng = np.random.default_rng(12)
+    for v in rng.choice(mesh.num_vertices, 12, replace=False):
+        nbr, vals, dirichlet = row_at(mesh.macro_xyz, mesh.cells, 3,
+                                      mesh.keys[v], kappa=kappa)
+        assert dirichlet == bool(S.dirichlet[v])
+        dense = S.A[v].toarray().ravel()
+        assert np.abs(dense[mesh.index_of(nbr)] - vals).max() <= 1e-15
