@@ -14,6 +14,10 @@ ways:
   at cell-interior points, A is symmetric, restriction is the transpose of
   prolongation, and a V(2,2) solve reaches 1e-10 in both precisions.
 
+The variable-coefficient operator div(k grad) gets the same treatment:
+sampled rows (the oracle's row with the coefficient values the GPU read)
+and constants annihilated on interior rows.
+
 Inputs are drawn with torch's generator on the device; the oracle reads
 them at owner copies, which no library kernel writes.
 """
@@ -375,3 +379,83 @@ def test_fmg_unit_cube_reaches_discretisation_error():
     err = (u - ch * s)[interior].abs().max().item()
     assert err <= 0.25 * disc, (err, disc)
     m.close()
+
+
+# ------------------------------------------------ variable coefficient --
+@pytest.fixture(scope="module")
+def kappa(big):
+    """k = 1 + sin(2 pi x) sin(2 pi y) sin(2 pi z) / 2 at the slots' own
+    coordinates, made consistent."""
+    X = torch.zeros(3 * big.nslot, dtype=torch.float64, device="cuda")
+    big.m.coords_device(LEVEL, X)
+    X = X.view(-1, 3)
+    w = 2.0 * np.pi
+    k = 1.0 + 0.5 * (torch.sin(w * X[:, 0]) * torch.sin(w * X[:, 1]) *
+                     torch.sin(w * X[:, 2]))
+    del X
+    big.m.sync(LEVEL, k)
+    yield k
+    del k
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def krows(big, kappa):
+    """Oracle rows of div(k grad) at the structured sample points, with the
+    coefficient values the GPU holds at the micro-tets' vertices."""
+    cache = {}
+
+    def kvals(tkeys):
+        flat = tkeys.reshape(-1, 8)
+        slots = []
+        for kk in flat:
+            t = tuple(kk)
+            if t not in cache:
+                cache[t] = big.slot_of_key(kk)
+            slots.append(cache[t])
+        return big.gather(kappa, slots).reshape(tkeys.shape[:-1])
+
+    out = []
+    for (c, i, j, k) in sample_points(random_count=0):
+        slot = big.m.slot_index(LEVEL, c, i, j, k)
+        key, _ = big.m.keys(LEVEL, slot, 1)
+        nbr, vals, dirichlet = row_at(big.xyz, big.cells, LEVEL, key[0],
+                                      kappa=kvals)
+        nslots = np.array([big.slot_of_key(kk) for kk in nbr])
+        out.append(Row(slot, big.slot_of_key(key[0]), nslots, vals, dirichlet))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_divkgrad_sampled_rows(big, kappa, krows, dtype):
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    # FP32: the bound of the small-size parity tests (about 100 roundings of
+    # O(1) terms per row)
+    tol = FP64_TOL if dtype == "f64" else 3e-5
+    x = big.rand(14, tdt)
+    k = kappa.to(tdt)
+    y = torch.full_like(x, float("nan"))
+    big.m.apply_divkgrad(LEVEL, k, x, y)
+    got = big.gather(y, [r.slot for r in krows])
+    assert np.isfinite(got).all()
+    assert np.array_equal(got, big.gather(y, [r.own for r in krows]))
+    for r, g in zip(krows, got):
+        xv = big.gather(x, r.nslots)
+        want = 0.0 if r.dirichlet else float(r.vals @ xv)
+        assert abs(g - want) <= tol * float(np.abs(r.vals) @ np.abs(xv)), \
+            (r.slot, g, want)
+    del x, k, y
+    torch.cuda.empty_cache()
+
+
+def test_divkgrad_annihilates_constants(big, kappa):
+    """Rows of div(k grad) sum to zero: A_k 1 = 0 on every interior row."""
+    u = torch.ones_like(kappa)
+    y = torch.full_like(u, float("nan"))
+    big.m.apply_divkgrad(LEVEL, kappa, u, y)
+    mask = big.interior_mask()
+    stencil_sum = np.abs(big.m.cell_stencils(LEVEL)).sum(axis=2).max()
+    worst = y[mask].abs().max().item()
+    assert worst <= FP64_TOL * 30 * 1.5 * stencil_sum
+    del u, y
+    torch.cuda.empty_cache()
