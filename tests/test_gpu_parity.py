@@ -69,6 +69,39 @@ def test_apply_fp32(name, level):
     assert err <= FP32_TOL
 
 
+@pytest.mark.parametrize("name,level,probes", [("kuhn_cube", 2, None),
+                                               ("jittered_288", 1, None),
+                                               ("jittered_288", 2, None),
+                                               ("jittered_288", 3, 64)])
+def test_apply_brute_force_matrix(name, level, probes):
+    """The GPU operator as a matrix: columns from unit vectors on every
+    interior DoF (or, with `probes`, seeded random vectors) against the
+    oracle's interior block A_II."""
+    P = pair(name, level, level)
+    S = P.S(level)
+    AII, I = S.interior_matrix()
+    AII = AII.toarray()
+    idx, _ = P.slot_map(level)
+    idx_t = torch.as_tensor(idx, device="cuda")
+    y = torch.zeros(len(idx), dtype=torch.float64, device="cuda")
+    scale = np.abs(AII).max()
+    if probes is None:
+        for c, v in enumerate(I):
+            x = (idx_t == int(v)).double()
+            P.m.apply(level, x, y)
+            col = P.from_gpu(level, y)[I]
+            assert np.abs(col - AII[:, c]).max() <= 1e-13 * scale, (v, c)
+    else:
+        rng = np.random.default_rng(31)
+        for _ in range(probes):
+            xv = np.zeros(S.mesh.num_vertices)
+            xv[I] = rng.uniform(-1.0, 1.0, len(I))
+            P.m.apply(level, P.to_gpu(level, xv), y)
+            got = P.from_gpu(level, y)[I]
+            want = AII @ xv[I]
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
 def test_apply_is_deterministic():
     P = pair("jittered_288", 4, 4)
     x = P.to_gpu(4, fields.uniform_values(P.S(4).mesh.num_vertices, 9))
