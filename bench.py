@@ -98,40 +98,45 @@ def batch_leg(ht, torch):
     create_s = time.time() - t0
     info = batch.info()
 
-    def run_batch():
+    def run_batch(prec):
         us = [torch.zeros_like(b) for b in bs]
         torch.cuda.synchronize()
-        st = batch.solve(us, bs, rel_tol=1e-10, max_cycles=100)
+        st = batch.solve(us, bs, rel_tol=1e-10, max_cycles=100, precision=prec)
         return us, st
 
-    def run_loop():
+    def run_loop(prec):
         us = [torch.zeros_like(b) for b in bs]
         torch.cuda.synchronize()
         t1 = time.time()
-        st = [m.solve(p.level, u, b, ht.HT_PREC_F64, 1e-10, 100)
+        st = [m.solve(p.level, u, b, prec, 1e-10, 100)
               for m, p, u, b in zip(meshes, probs, us, bs)]
         torch.cuda.synchronize()
         return us, st, time.time() - t1
 
-    run_batch()
-    ub, stb = run_batch()
-    run_loop()
-    ul, stl, loop_s = run_loop()
-    batch_s = stb[0]["seconds"]
-    diff = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(ub, ul))
-    return {"workload": "256 problems (Kuhn boxes <= 4 cubes, jittered slabs; "
-                        "levels 3-6; seed 6), FP64 V(2,2) to 1e-10",
-            "problems": info["problems"], "cells": info["cells"],
-            "dofs": info["dofs"], "batch_seconds": round(batch_s, 4),
-            "loop_seconds": round(loop_s, 4),
-            "speedup_vs_loop": round(loop_s / batch_s, 2),
-            "solves_per_s": round(info["problems"] / batch_s, 1),
-            "gdofs_solved_per_s": round(info["dofs"] / batch_s / 1e9, 4),
-            "cycles_max": max(x["cycles"] for x in stb),
-            "cycles_equal_to_loop": sum(a["cycles"] == b["cycles"]
-                                        for a, b in zip(stb, stl)),
-            "max_rel_diff_vs_loop": diff,
-            "create_seconds": round(create_s, 3)}
+    out = {"workload": "256 problems (Kuhn boxes <= 4 cubes, jittered slabs; "
+                       "levels 3-6; seed 6), V(2,2) to 1e-10: FP32-in-FP64 "
+                       "refinement and FP64",
+           "problems": info["problems"], "cells": info["cells"],
+           "dofs": info["dofs"], "create_seconds": round(create_s, 3)}
+    for name, prec in (("mixed", ht.HT_PREC_MIXED), ("f64", ht.HT_PREC_F64)):
+        run_batch(prec)
+        ub, stb = run_batch(prec)
+        run_loop(prec)
+        ul, stl, loop_s = run_loop(prec)
+        batch_s = stb[0]["seconds"]
+        diff = max(float((a - b).abs().max() / b.abs().max())
+                   for a, b in zip(ub, ul))
+        out[name] = {"batch_seconds": round(batch_s, 4),
+                     "loop_seconds": round(loop_s, 4),
+                     "speedup_vs_loop": round(loop_s / batch_s, 2),
+                     "solves_per_s": round(info["problems"] / batch_s, 1),
+                     "gdofs_solved_per_s": round(info["dofs"] / batch_s / 1e9, 4),
+                     "cycles_max": max(x["cycles"] for x in stb),
+                     "cycles_equal_to_loop": sum(a["cycles"] == b["cycles"]
+                                                 for a, b in zip(stb, stl)),
+                     "max_rel_diff_vs_loop": diff}
+        del ub, ul
+    return out
 
 
 def divkgrad_leg(mesh, L, x, ndof, args, stream):

@@ -261,8 +261,11 @@ int ht_batch_query(const ht_batch* batch, int* n_problems, int64_t* n_dofs,
  * its own relative residual is <= rel_tol; its result is the iterate of
  * the cycle at which it converged (later cycles of the batch do not change
  * it), so it equals what ht_solve computes for that problem alone, up to
- * rounding.  stats: array of n, one per problem.  opts->precision must be
- * HT_PREC_F64 and opts->cyc.coarse_level must not exceed any problem's
+ * rounding.  stats: array of n, one per problem.  opts->precision:
+ * HT_PREC_F64 (FP64 V-cycles) or HT_PREC_MIXED (FP32-in-FP64 iterative
+ * refinement as in ht_solve: FP32 correction cycles of all problems in one
+ * batched V-cycle, FP64 residuals, norms and updates).  The Jacobi smoother
+ * is required, and opts->cyc.coarse_level must not exceed any problem's
  * finest level.  Synchronises once per cycle.  HT_ERR_NOT_CONVERGED if
  * some problem did not converge (all stats filled, all u[p] written). */
 int ht_batch_solve(ht_batch* batch, const ht_solve_opts* opts,

@@ -345,15 +345,17 @@ class Batch:
 
     def solve(self, us, bs, rel_tol=1e-10, max_cycles=100, nu1=2, nu2=2,
               omega=2.0 / 3.0, coarse_level=2, use_graph=True,
-              raise_on_fail=True):
+              raise_on_fail=True, precision=HT_PREC_F64):
         """Solve every problem; us[p], bs[p] are float64 device vectors of
-        problem p's mesh at its finest level.  Returns per-problem stats."""
+        problem p's mesh at its finest level.  precision: HT_PREC_F64 or
+        HT_PREC_MIXED (FP32-in-FP64 refinement).  Returns per-problem
+        stats."""
         if len(us) != self.n or len(bs) != self.n:
             raise ValueError("need one u and one b per problem")
         up = (C.c_void_p * self.n)(*[_ptr(u).value for u in us])
         bp = (C.c_void_p * self.n)(*[_ptr(b).value for b in bs])
         o = _lib.SolveOpts(Mesh.cycle_opts(nu1, nu2, omega, coarse_level),
-                           HT_PREC_F64, rel_tol, max_cycles, int(use_graph))
+                           precision, rel_tol, max_cycles, int(use_graph))
         st = (_lib.SolveStats * self.n)()
         code = load().ht_batch_solve(self._h, C.byref(o), up, bp, st,
                                      _stream())

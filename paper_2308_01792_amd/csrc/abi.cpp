@@ -842,46 +842,50 @@ static void batch_norms(ht_mesh* h, Batch& bt, int which, hipStream_t s) {
                               hipMemcpyDeviceToHost, s));
 }
 
-// One V-cycle over absolute levels.  On level l the problems [0, pd1[l])
-// are active: those with a finer finest level carry a coarse correction
-// (zero initial guess, right-hand side restricted from l + 1), those whose
-// finest level is l carry their iterate.  The result is left in work(l).u.
+// One V-cycle over absolute levels in `dtype`.  On level l the problems
+// [0, pd1[l]) are active: those with a finer finest level carry a coarse
+// correction (zero initial guess, right-hand side restricted from l + 1),
+// those whose finest level is l carry their iterate.  A correction cycle
+// (the FP32 cycle of the refinement) starts every problem from zero: there
+// each problem's right-hand side at its finest level is its FP64 residual
+// rounded to FP32.  The result is left in work(l).u.
 static void batch_level(ht_mesh* h, Batch& bt, int l, const ht_cycle_opts& o,
-                        hipStream_t s) {
+                        int dtype, bool correction, hipStream_t s) {
   Mesh& m = h->m;
-  LevelWork& w = work(h, l, HT_F64);
+  LevelWork& w = work(h, l, dtype);
   if (l == o.coarse_level) {
-    coarse_fast(h, l, HT_F64, w.b, w.u, s);
+    coarse_fast(h, l, dtype, w.b, w.u, s);
     return;
   }
+  const int pz = correction ? bt.pd1[l] : bt.pd0[l];
   const Range A = problem_range(m, 0, bt.pd1[l]);
-  const Range C = problem_range(m, 0, bt.pd0[l]);
-  const Range D = problem_range(m, bt.pd0[l], bt.pd1[l]);
+  const Range C = problem_range(m, 0, pz);          // zero initial guess
+  const Range D = problem_range(m, pz, bt.pd1[l]);  // iterate carried
   void* cur = w.u;
   void* oth = w.t;
   int todo = o.nu1;
   if (todo > 0) {
-    zero_guess_sweep(h, l, HT_F64, o.omega, oth, w.b, s, C);
-    op_pass(h, l, HT_F64, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, D);
+    zero_guess_sweep(h, l, dtype, o.omega, oth, w.b, s, C);
+    op_pass(h, l, dtype, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, D);
     std::swap(cur, oth);
     --todo;
   } else {
-    flat_range(h, l, HT_F64, HT_F64, FOP_ZERO, cur, nullptr, s, C);
+    flat_range(h, l, dtype, dtype, FOP_ZERO, cur, nullptr, s, C);
   }
   for (; todo > 0; --todo) {
-    op_pass(h, l, HT_F64, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, A);
+    op_pass(h, l, dtype, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, A);
     std::swap(cur, oth);
   }
-  op_pass(h, l, HT_F64, OP_RESID, cur, oth, w.b, 0.0, s, false, 0, A);
-  LevelWork& wc = work(h, l - 1, HT_F64);
-  restrict_pass(h, l, HT_F64, oth, wc.b, s, A);
-  batch_level(h, bt, l - 1, o, s);
-  prolong_pass(h, l - 1, HT_F64, wc.u, cur, s, A);
+  op_pass(h, l, dtype, OP_RESID, cur, oth, w.b, 0.0, s, false, 0, A);
+  LevelWork& wc = work(h, l - 1, dtype);
+  restrict_pass(h, l, dtype, oth, wc.b, s, A);
+  batch_level(h, bt, l - 1, o, dtype, correction, s);
+  prolong_pass(h, l - 1, dtype, wc.u, cur, s, A);
   for (int k = 0; k < o.nu2; ++k) {
-    op_pass(h, l, HT_F64, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, A);
+    op_pass(h, l, dtype, OP_JACOBI, cur, oth, w.b, o.omega, s, false, 0, A);
     std::swap(cur, oth);
   }
-  if (cur != w.u) flat_range(h, l, HT_F64, HT_F64, FOP_COPY, w.u, cur, s, A);
+  if (cur != w.u) flat_range(h, l, dtype, dtype, FOP_COPY, w.u, cur, s, A);
 }
 
 }  // namespace ht
@@ -1511,8 +1515,9 @@ int ht_batch_solve(ht_batch* B, const ht_solve_opts* o, void* const* u,
     Mesh& m = h->m;
     Batch& bt = B->bt;
     const int P = bt.nprob;
-    if (o->precision != HT_PREC_F64)
-      throw Error{HT_ERR_ARG, "batch solves run in FP64 (HT_PREC_F64)"};
+    if (o->precision != HT_PREC_F64 && o->precision != HT_PREC_MIXED)
+      throw Error{HT_ERR_ARG, "precision must be HT_PREC_F64 or HT_PREC_MIXED"};
+    const bool mixed = o->precision == HT_PREC_MIXED;
     if (o->cyc.smoother != HT_SMOOTH_JACOBI)
       throw Error{HT_ERR_ARG, "batch solves use the Jacobi smoother"};
     if (o->max_cycles < 0 || o->max_cycles > 256)
@@ -1529,7 +1534,10 @@ int ht_batch_solve(ht_batch* B, const ht_solve_opts* o, void* const* u,
     const auto t0 = std::chrono::steady_clock::now();
     // set-up before any capture: workspace, coarse solver, norm tables
     coarse_solver(h, o->cyc.coarse_level);
-    for (int l = o->cyc.coarse_level; l <= bt.lmax; ++l) work(h, l, HT_F64);
+    for (int l = o->cyc.coarse_level; l <= bt.lmax; ++l) {
+      work(h, l, HT_F64);
+      if (mixed) work(h, l, HT_F32);
+    }
     if (!bt.d_part) {
       bt.part_off.assign(bt.lmax + 1, 0);
       int64_t off = 0;
@@ -1574,7 +1582,18 @@ int ht_batch_solve(ht_batch* B, const ht_solve_opts* o, void* const* u,
       const double bn = std::sqrt(bt.h_norm2[p]);
       scale[p] = bn > 0 ? 1.0 / bn : 1.0;
     }
+    // mixed: each problem's FP64 residual (left in work(l).t by the norms
+    // at its finest level l) rounded to FP32, the right-hand side of the
+    // next correction cycle
+    auto residuals_to_f32 = [&](hipStream_t ss) {
+      for (int l = bt.lmax; l >= bt.lmin; --l) {
+        if (bt.pd1[l] <= bt.pd0[l]) continue;
+        flat_range(h, l, HT_F32, HT_F64, FOP_COPY, work(h, l, HT_F32).b,
+                   work(h, l, HT_F64).t, ss, problem_range(m, bt.pd0[l], bt.pd1[l]));
+      }
+    };
     batch_norms(h, bt, 0, s);
+    if (mixed) residuals_to_f32(s);
     HT_CHECK_HIP(hipStreamSynchronize(s));
     std::vector<ht_solve_stats> ps(P);
     for (auto& x : ps) std::memset(&x, 0, sizeof(x));
@@ -1603,11 +1622,24 @@ int ht_batch_solve(ht_batch* B, const ht_solve_opts* o, void* const* u,
     };
     record(0);
     std::ostringstream key;
-    key << "batch:" << o->cyc.nu1 << ':' << o->cyc.nu2 << ':' << o->cyc.omega
-        << ':' << o->cyc.coarse_level;
+    key << "batch:" << o->precision << ':' << o->cyc.nu1 << ':' << o->cyc.nu2
+        << ':' << o->cyc.omega << ':' << o->cyc.coarse_level;
     auto step = [&](hipStream_t ss) {
-      batch_level(h, bt, bt.lmax, o->cyc, ss);
+      if (!mixed) {
+        batch_level(h, bt, bt.lmax, o->cyc, HT_F64, false, ss);
+        batch_norms(h, bt, 0, ss);
+        return;
+      }
+      // FP32 correction cycle, FP64 update u += c at every problem's finest
+      // level, FP64 residuals and norms, residuals rounded to FP32
+      batch_level(h, bt, bt.lmax, o->cyc, HT_F32, true, ss);
+      for (int l = bt.lmax; l >= bt.lmin; --l) {
+        if (bt.pd1[l] <= bt.pd0[l]) continue;
+        flat_range(h, l, HT_F64, HT_F32, FOP_ADD, work(h, l, HT_F64).u,
+                   work(h, l, HT_F32).u, ss, problem_range(m, bt.pd0[l], bt.pd1[l]));
+      }
       batch_norms(h, bt, 0, ss);
+      residuals_to_f32(ss);
     };
     int k = 0;
     while (open > 0 && k < o->max_cycles) {

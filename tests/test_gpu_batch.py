@@ -36,11 +36,11 @@ def setup():
     return meshes, bs, batch
 
 
-def _individual(meshes, bs, **kw):
+def _individual(meshes, bs, precision=ht.HT_PREC_F64, **kw):
     out = []
     for m, b, p in zip(meshes, bs, PROBLEMS):
         u = torch.zeros_like(b)
-        st = m.solve(p.level, u, b, ht.HT_PREC_F64, **kw)
+        st = m.solve(p.level, u, b, precision, **kw)
         out.append((u, st))
     return out
 
@@ -97,6 +97,48 @@ def test_graph_replay_is_bitwise_eager(setup):
     for g in (False, True, True):
         us = [torch.zeros_like(b) for b in bs]
         st = batch.solve(us, bs, rel_tol=1e-10, max_cycles=100, use_graph=g)
+        res.append((us, [s["history"] for s in st]))
+    for us, hist in res[1:]:
+        assert hist == res[0][1]
+        assert all(torch.equal(a, b) for a, b in zip(us, res[0][0]))
+
+
+# ------------------------------------------ FP32-in-FP64 refinement --
+def test_mixed_fixed_cycles_give_the_individual_iterates(setup):
+    """Three refinement steps: FP32 correction cycles of all problems in one
+    batched V-cycle give each problem the iterate of its own mixed solve."""
+    meshes, bs, batch = setup
+    kw = dict(rel_tol=0.0, max_cycles=3, raise_on_fail=False)
+    ref = _individual(meshes, bs, ht.HT_PREC_MIXED, **kw)
+    us = [torch.zeros_like(b) for b in bs]
+    st = batch.solve(us, bs, precision=ht.HT_PREC_MIXED, **kw)
+    for p, (u, (ur, sr)) in enumerate(zip(us, ref)):
+        assert st[p]["cycles"] == 3
+        assert np.allclose(st[p]["history"], sr["history"], rtol=1e-12, atol=0)
+        assert rel_err(u.cpu().numpy(), ur.cpu().numpy()) <= 1e-12, p
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_mixed_batch_solve_matches_individual_solves(setup, use_graph):
+    meshes, bs, batch = setup
+    ref = _individual(meshes, bs, ht.HT_PREC_MIXED, rel_tol=1e-10,
+                      max_cycles=100)
+    us = [torch.zeros_like(b) for b in bs]
+    st = batch.solve(us, bs, rel_tol=1e-10, max_cycles=100,
+                     use_graph=use_graph, precision=ht.HT_PREC_MIXED)
+    for p, (u, (ur, sr)) in enumerate(zip(us, ref)):
+        assert st[p]["converged"] and st[p]["rel_res"] <= 1e-10
+        assert abs(st[p]["cycles"] - sr["cycles"]) <= 1
+        assert rel_err(u.cpu().numpy(), ur.cpu().numpy()) <= 1e-9, p
+
+
+def test_mixed_graph_replay_is_bitwise_eager(setup):
+    _, bs, batch = setup
+    res = []
+    for g in (False, True, True):
+        us = [torch.zeros_like(b) for b in bs]
+        st = batch.solve(us, bs, rel_tol=1e-10, max_cycles=100, use_graph=g,
+                         precision=ht.HT_PREC_MIXED)
         res.append((us, [s["history"] for s in st]))
     for us, hist in res[1:]:
         assert hist == res[0][1]

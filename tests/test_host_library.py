@@ -203,9 +203,12 @@ def test_batch_create_and_errors(lib):
     # options are checked before any device call
     fake = (C.c_void_p * n)(*([256] * n))
     st = (_lib.SolveStats * n)()
-    o = _lib.SolveOpts(_lib.CycleOpts(2, 2, 2.0 / 3.0, 2), ht.HT_PREC_MIXED,
-                       1e-10, 10, 1)
+    o = _lib.SolveOpts(_lib.CycleOpts(2, 2, 2.0 / 3.0, 2), 7, 1e-10, 10, 1)
     assert lib.ht_batch_solve(b._h, C.byref(o), fake, fake, st, None) == _lib.HT_ERR_ARG
+    o.precision = ht.HT_PREC_MIXED
+    o.cyc.smoother = ht.HT_SMOOTH_CHEBYSHEV
+    assert lib.ht_batch_solve(b._h, C.byref(o), fake, fake, st, None) == _lib.HT_ERR_ARG
+    o.cyc.smoother = ht.HT_SMOOTH_JACOBI
     o.precision = ht.HT_PREC_F64
     o.cyc.coarse_level = min(p.level for p in probs) + 1
     assert lib.ht_batch_solve(b._h, C.byref(o), fake, fake, st, None) == _lib.HT_ERR_LEVEL
