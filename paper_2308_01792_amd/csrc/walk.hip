@@ -204,13 +204,15 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_elem(ElemArgs a) {
       T bv[kWalkRows];
 #pragma unroll
       for (int r = 0; r < kWalkRows; ++r) bload(bv[r], r0, off[r]);
-      // rows off the faces j = 0 and k = 0 hold classes 0, 1 (i = 0) and
-      // 8 (i = e) only: select among three factors instead of a lookup
-      const T g0 = gz[wave][0], g1 = gz[wave][1], g8 = gz[wave][8];
+      // rows off the faces j = 0 and k = 0 hold classes 0, 1 (i = 0),
+      // 8 (i = e) and 9 (i = 0 = e) only: select among four factors
+      // instead of a lookup
+      const T g0 = gz[wave][0], g1 = gz[wave][1], g8 = gz[wave][8], g9 = gz[wave][9];
 #pragma unroll
       for (int r = 0; r < kWalkRows; ++r) {
         T f;
-        if (j0 + r > 0 && k > 0) f = (cl[r] & 1) ? g1 : ((cl[r] & 8) ? g8 : g0);
+        if (j0 + r > 0 && k > 0)
+          f = (cl[r] & 1) ? ((cl[r] & 8) ? g9 : g1) : ((cl[r] & 8) ? g8 : g0);
         else f = gz[wave][cl[r] < 0 ? 0 : cl[r]];
         bstore(f * bv[r], ro, off[r]);
       }
