@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <sstream>
+#include <tuple>
 
 #include "hytet_impl.hpp"
 #include "kernels.hpp"
@@ -39,7 +40,8 @@ struct Batch {
 struct ht_mesh {
   ht::Mesh m;
   // (level, J) -> tile list on the device
-  std::map<std::pair<int, int>, std::pair<int2*, int64_t>> tiles;
+  // (level, J, waves side by side in i) -> tile list on the device
+  std::map<std::tuple<int, int, bool>, std::pair<int2*, int64_t>> tiles;
   // level -> walk tiles (64 i x 8 rows) for the transfer / elementwise kernels
   std::map<int, std::pair<int2*, int64_t>> walk_tiles;
   std::map<std::pair<int, int>, int> tuned_J;  // (level, dtype) -> J
@@ -125,12 +127,13 @@ static const int kJ[] = {4, 8, 16};
 // untuned tile rows: 4 keeps the FP64 stencil kernels at three waves per SIMD
 static const int kDefaultJ = 4;
 
-// Tile groups of the stencil kernel: 62 output i x (kCellWaves x J rows).
-static std::vector<int2> make_tiles(int n, int J) {
+// Tile groups of the stencil kernel: 62 output i x (kCellWaves x J rows),
+// or (62 kCellWaves) i x J rows when the waves sit side by side in i.
+static std::vector<int2> make_tiles(int n, int J, bool in_i) {
   std::vector<int2> t;
-  const int G = kCellWaves * J;
-  for (int tj = 0; G * tj <= n; ++tj)
-    for (int ti = 0; 62 * ti + G * tj <= n; ++ti) t.push_back(make_int2(62 * ti, G * tj));
+  const int GJ = in_i ? J : kCellWaves * J, GI = in_i ? 62 * kCellWaves : 62;
+  for (int tj = 0; GJ * tj <= n; ++tj)
+    for (int ti = 0; GI * ti + GJ * tj <= n; ++ti) t.push_back(make_int2(GI * ti, GJ * tj));
   return t;
 }
 
@@ -145,7 +148,9 @@ static int64_t partials_needed(const ht_mesh* h, int level) {
   const Mesh& m = h->m;
   const int n = 1 << level;
   int64_t cell_blocks = 0;
-  for (int J : kJ) cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J).size());
+  for (int J : kJ)
+    for (bool in_i : {false, true})
+      cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J, in_i).size());
   const int64_t fp = n_tri(n - 2), total = m.n_faces * fp + m.n_edges * std::max(n - 1, 0) + m.n_verts;
   const int64_t exch_blocks = (total + 255) / 256;
   const int64_t elem_blocks = m.nc * (int64_t)make_walk_tiles(n).size();
@@ -206,10 +211,11 @@ void ensure_uploaded_h(ht_mesh* h) {
     std::vector<float> wf(w.begin(), w.end());
     m.d_w64[l] = upload(w);
     m.d_w32[l] = upload(wf);
-    for (int J : kJ) {
-      auto t = make_tiles(1 << l, J);
-      h->tiles[{l, J}] = {upload(t), (int64_t)t.size()};
-    }
+    for (int J : kJ)
+      for (bool in_i : {false, true}) {
+        auto t = make_tiles(1 << l, J, in_i);
+        h->tiles[{l, J, in_i}] = {upload(t), (int64_t)t.size()};
+      }
     {
       auto t = make_walk_tiles(1 << l);
       h->walk_tiles[l] = {upload(t), (int64_t)t.size()};
@@ -264,7 +270,7 @@ static int choose_J(ht_mesh* h, int level, int dtype) {
 static const void* level_weights(ht_mesh* h, int level, int dtype) {
   return dtype == HT_F64 ? (const void*)h->m.d_w64[level] : (const void*)h->m.d_w32[level];
 }
-static CellArgs cell_args(ht_mesh* h, int level, int dtype, int J,
+static CellArgs cell_args(ht_mesh* h, int level, int dtype, int J, int op,
                           const void* x, void* y, const void* b, double omega,
                           const Range& R) {
   Mesh& m = h->m;
@@ -276,7 +282,7 @@ static CellArgs cell_args(ht_mesh* h, int level, int dtype, int J,
   a.w = (const char*)level_weights(h, level, dtype) + R.c0 * 240 * (int64_t)esize(dtype);
   a.cls = m.d_cls + 16 * R.c0;
   a.partials = m.d_partials;
-  auto& t = h->tiles.at({level, J});
+  auto& t = h->tiles.at({level, J, cell_waves_in_i(op)});
   a.tiles = t.first;
   a.ntiles = t.second;
   a.nblocks = (R.c1 - R.c0) * t.second;
@@ -325,7 +331,7 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
   Mesh& m = h->m;
   if (R.empty()) return;
   const int J = choose_J(h, level, dtype);
-  CellArgs ca = cell_args(h, level, dtype, J, x, y, b, omega, R);
+  CellArgs ca = cell_args(h, level, dtype, J, op, x, y, b, omega, R);
   ca.y32 = at_cell(y32, R.c0, level, HT_F32);
   {
     const bool res = op == OP_RESID || op == OP_RESID32;
@@ -381,10 +387,11 @@ static const void* vcoef_couplings(ht_mesh* h, int level, int dtype) {
 }
 
 static const std::pair<int2*, int64_t>& tiles_of(ht_mesh* h, int level, int J) {
-  auto it = h->tiles.find({level, J});
+  auto it = h->tiles.find({level, J, false});
   if (it == h->tiles.end()) {
-    auto t = make_tiles(1 << level, J);
-    it = h->tiles.emplace(std::make_pair(level, J), std::make_pair(upload(t), (int64_t)t.size())).first;
+    auto t = make_tiles(1 << level, J, false);
+    it = h->tiles.emplace(std::make_tuple(level, J, false),
+                          std::make_pair(upload(t), (int64_t)t.size())).first;
   }
   return it->second;
 }
@@ -500,7 +507,7 @@ static void restrict_pass(ht_mesh* h, int fine, int dtype, const void* rf,
   if (R.empty()) return;
   const CellLayout Lc = make_layout(fine - 1);
   const int J = choose_J(h, fine, dtype);
-  CellArgs ca = cell_args(h, fine, dtype, J, rf, nullptr, nullptr, 0.0, R);
+  CellArgs ca = cell_args(h, fine, dtype, J, OP_RESTRICT, rf, nullptr, nullptr, 0.0, R);
   ca.y = at_cell(rc, R.c0, fine - 1, dtype);
   ca.stride_out = Lc.stride;
   ca.off_s0_out = Lc.off_s0;
@@ -707,7 +714,7 @@ static void cheb_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   Mesh& m = h->m;
   const Range R = full_range(m);
   const int J = choose_J(h, level, dtype);
-  CellArgs ca = cell_args(h, level, dtype, J, x, y, b, 1.0, R);
+  CellArgs ca = cell_args(h, level, dtype, J, OP_CHEB, x, y, b, 1.0, R);
   ca.d = at_cell(d, R.c0, level, dtype);
   ca.c1 = c1;
   ca.c2 = c2;

@@ -55,9 +55,10 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   // (class 1, offsets 0 3 4 5 6 11 12) and i + j + k = n (class 8, offsets
   // 0 7 8 9 10 11 12), in that order
   __shared__ T dwtab[14];
-  // A workgroup is kCellWaves waves on vertically adjacent tiles of one cell
-  // (rows j0 .. j0 + kCellWaves J - 1): the waves march in near lockstep on
-  // one CU, so each wave's halo rows are its neighbours' rows, fetched once.
+  // A workgroup is kCellWaves waves on adjacent tiles of one cell, marching
+  // in near lockstep on one CU: stacked in j (rows j0 .. j0 + kCellWaves J
+  // - 1), each wave's halo rows are its neighbours' rows, fetched once; side
+  // by side in i (cell_waves_in_i), each row is one contiguous run.
   // XCD-aware block order: block b runs on XCD b % 8; give each XCD a
   // contiguous run of (cell, tile group) work so neighbouring groups share
   // an L2.
@@ -72,7 +73,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   // derived from it lives in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t w = wb * kCellWaves + wave;  // partial-sum slot of this wave
-  const int i0 = tile.x, j0 = tile.y + wave * J;
+  constexpr bool IN_I = cell_waves_in_i(OP);
+  const int i0 = tile.x + (IN_I ? 62 * wave : 0), j0 = tile.y + (IN_I ? 0 : wave * J);
   const int n = a.n;
   const int64_t bytes = a.stride * (int64_t)sizeof(T);
   const int64_t ostride = RESTR ? a.stride_out : a.stride;
