@@ -375,6 +375,8 @@ def main():
         "stream_copy": {"ms": round(copy_ms, 4), "gbs": round(copy_gbs, 1),
                         "bytes": copy_bytes, "kernel": "k_flat<double, double, copy>"},
         "tile_rows": {"f64": rows64, "f32": rows32},
+        "sweep_shape": {name: dict(zip(("rows", "waves_in_i"), mesh.sweep_shape(L, code)))
+                        for name, code in (("f64", ht.HT_F64), ("f32", ht.HT_F32))},
         "kernel_ms": {"cell_apply": round(cell_avg, 4),
                       "exchange": round(exch_avg, 4)},
         "apply_f32": {"ms": round(ms32, 4),

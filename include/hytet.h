@@ -299,14 +299,25 @@ int ht_fmg(ht_mesh* mesh, int level, const ht_cycle_opts* opts, int cycles,
 
 /* ------------------------------------------------------------- tuning -- */
 /* The stencil kernel runs one wavefront per tile of 64 i-points x R rows,
- * marching in k.  R in {4, 8, 16} trades register pressure against halo
- * re-reads.  ht_set_tile_rows fixes R for (level, dtype); ht_get_tile_rows
- * reports the current choice (default 4). */
+ * marching in k, four wavefronts per workgroup.  R in {4, 8, 16} trades
+ * register pressure against halo re-reads.  ht_set_tile_rows fixes R for
+ * the apply and the restriction at (level, dtype) (waves stacked in j);
+ * ht_get_tile_rows reports the current choice (default 4). */
 int ht_set_tile_rows(ht_mesh* mesh, int level, int dtype, int rows);
 int ht_get_tile_rows(const ht_mesh* mesh, int level, int dtype, int* rows);
+/* Tile shape of the sweep operations (residual, Jacobi, FP32 residual,
+ * Chebyshev step), which also stream b: R rows per wave and the workgroup's
+ * arrangement, waves_in_i = 1 for its four waves side by side in i (one
+ * contiguous run of 248 points per row), 0 for stacked in j.  Default
+ * R = 4, waves_in_i = 1.  Results do not depend on the shape. */
+int ht_set_sweep_shape(ht_mesh* mesh, int level, int dtype, int rows,
+                       int waves_in_i);
+int ht_get_sweep_shape(const ht_mesh* mesh, int level, int dtype, int* rows,
+                       int* waves_in_i);
 /* Autotuner: times every R on the live apply at (level, dtype) on `stream`
- * (two scratch vectors are allocated and freed), keeps the fastest and
- * returns it in *rows.  With cache_path != NULL a text cache keyed by
+ * and every (R, arrangement) on the live Jacobi sweep (three scratch
+ * vectors are allocated and freed), keeps the fastest of each and returns the
+ * apply's R in *rows.  With cache_path != NULL a text cache keyed by
  * (gfx arch, level, dtype, cells, cell stride) is read first and appended
  * to after tuning.  Synchronises. */
 int ht_autotune(ht_mesh* mesh, int level, int dtype, const char* cache_path,

@@ -285,6 +285,18 @@ class Mesh:
         check(load().ht_get_tile_rows(self._h, level, dtype_code, C.byref(r)))
         return r.value
 
+    def set_sweep_shape(self, level: int, dtype_code: int, rows: int,
+                        waves_in_i: bool):
+        check(load().ht_set_sweep_shape(self._h, level, dtype_code, rows,
+                                        int(waves_in_i)))
+
+    def sweep_shape(self, level: int, dtype_code: int):
+        """(rows per wave, waves side by side in i) of the sweep operations."""
+        r, w = C.c_int(), C.c_int()
+        check(load().ht_get_sweep_shape(self._h, level, dtype_code,
+                                        C.byref(r), C.byref(w)))
+        return r.value, bool(w.value)
+
     def autotune(self, level: int, dtype_code: int, cache_path=None) -> int:
         r = C.c_int()
         check(load().ht_autotune(self._h, level, dtype_code,

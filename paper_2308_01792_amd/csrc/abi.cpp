@@ -45,6 +45,8 @@ struct ht_mesh {
   // level -> walk tiles (64 i x 8 rows) for the transfer / elementwise kernels
   std::map<int, std::pair<int2*, int64_t>> walk_tiles;
   std::map<std::pair<int, int>, int> tuned_J;  // (level, dtype) -> J
+  // (level, dtype) -> (J, waves side by side in i) of the sweep operations
+  std::map<std::pair<int, int>, std::pair<int, bool>> tuned_sweep;
   std::map<int, double> lambda_max;            // level -> estimate
   bool capturing = false;
 };
@@ -265,12 +267,27 @@ static int choose_J(ht_mesh* h, int level, int dtype) {
   return kDefaultJ;
 }
 
+// Tile shape of a stencil launch: rows per wave and wave arrangement.  The
+// apply and the restriction stack the waves in j with the tuned J; the
+// sweep operations use their own tuned shape, by default four rows with the
+// waves side by side in i (measured faster for them at the largest levels).
+struct Shape {
+  int J;
+  bool in_i;
+};
+static Shape choose_shape(ht_mesh* h, int level, int dtype, int op) {
+  if (!op_is_sweep(op)) return Shape{choose_J(h, level, dtype), false};
+  auto it = h->tuned_sweep.find({level, dtype});
+  if (it != h->tuned_sweep.end()) return Shape{it->second.first, it->second.second};
+  return Shape{kDefaultJ, true};
+}
+
 // Stencil-kernel arguments over the cells of R: every per-cell array is
 // addressed from the range's first cell.
 static const void* level_weights(ht_mesh* h, int level, int dtype) {
   return dtype == HT_F64 ? (const void*)h->m.d_w64[level] : (const void*)h->m.d_w32[level];
 }
-static CellArgs cell_args(ht_mesh* h, int level, int dtype, int J, int op,
+static CellArgs cell_args(ht_mesh* h, int level, int dtype, const Shape& sh,
                           const void* x, void* y, const void* b, double omega,
                           const Range& R) {
   Mesh& m = h->m;
@@ -282,7 +299,8 @@ static CellArgs cell_args(ht_mesh* h, int level, int dtype, int J, int op,
   a.w = (const char*)level_weights(h, level, dtype) + R.c0 * 240 * (int64_t)esize(dtype);
   a.cls = m.d_cls + 16 * R.c0;
   a.partials = m.d_partials;
-  auto& t = h->tiles.at({level, J, cell_waves_in_i(op)});
+  auto& t = h->tiles.at({level, sh.J, sh.in_i});
+  a.waves_in_i = sh.in_i ? 1 : 0;
   a.tiles = t.first;
   a.ntiles = t.second;
   a.nblocks = (R.c1 - R.c0) * t.second;
@@ -330,13 +348,13 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
                     void* y32 = nullptr) {
   Mesh& m = h->m;
   if (R.empty()) return;
-  const int J = choose_J(h, level, dtype);
-  CellArgs ca = cell_args(h, level, dtype, J, op, x, y, b, omega, R);
+  const Shape sh = choose_shape(h, level, dtype, op);
+  CellArgs ca = cell_args(h, level, dtype, sh, x, y, b, omega, R);
   ca.y32 = at_cell(y32, R.c0, level, HT_F32);
   {
     const bool res = op == OP_RESID || op == OP_RESID32;
     Prof p(h, op == OP_APPLY ? "cell_apply" : res ? "cell_residual" : "cell_jacobi", s);
-    launch_cell(dtype, op, J, ca, s);
+    launch_cell(dtype, op, sh.J, ca, s);
     check_launch();
   }
   ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
@@ -506,15 +524,15 @@ static void restrict_pass(ht_mesh* h, int fine, int dtype, const void* rf,
   Mesh& m = h->m;
   if (R.empty()) return;
   const CellLayout Lc = make_layout(fine - 1);
-  const int J = choose_J(h, fine, dtype);
-  CellArgs ca = cell_args(h, fine, dtype, J, OP_RESTRICT, rf, nullptr, nullptr, 0.0, R);
+  const Shape sh = choose_shape(h, fine, dtype, OP_RESTRICT);
+  CellArgs ca = cell_args(h, fine, dtype, sh, rf, nullptr, nullptr, 0.0, R);
   ca.y = at_cell(rc, R.c0, fine - 1, dtype);
   ca.stride_out = Lc.stride;
   ca.off_s0_out = Lc.off_s0;
   ca.off_s1_out = Lc.off_s1;
   {
     Prof p(h, "restrict", s);
-    launch_cell(dtype, OP_RESTRICT, J, ca, s);
+    launch_cell(dtype, OP_RESTRICT, sh.J, ca, s);
     check_launch();
   }
   ExchArgs ea = exch_args(h, fine - 1, rc, nullptr, nullptr, 0.0, m.d_partials, R);
@@ -713,14 +731,14 @@ static void cheb_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
                       hipStream_t s) {
   Mesh& m = h->m;
   const Range R = full_range(m);
-  const int J = choose_J(h, level, dtype);
-  CellArgs ca = cell_args(h, level, dtype, J, OP_CHEB, x, y, b, 1.0, R);
+  const Shape sh = choose_shape(h, level, dtype, OP_CHEB);
+  CellArgs ca = cell_args(h, level, dtype, sh, x, y, b, 1.0, R);
   ca.d = at_cell(d, R.c0, level, dtype);
   ca.c1 = c1;
   ca.c2 = c2;
   {
     Prof p(h, "cell_chebyshev", s);
-    launch_cell(dtype, OP_CHEB, J, ca, s);
+    launch_cell(dtype, OP_CHEB, sh.J, ca, s);
     check_launch();
   }
   ExchArgs ea = exch_args(h, level, y, x, b, 1.0, m.d_partials + kCellWaves * ca.nblocks, R);
@@ -1694,32 +1712,59 @@ int ht_get_tile_rows(const ht_mesh* h, int level, int dtype, int* rows) {
   });
 }
 
+int ht_set_sweep_shape(ht_mesh* h, int level, int dtype, int rows, int waves_in_i) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    check_level(h->m, level);
+    check_dtype(dtype);
+    if (rows != 4 && rows != 8 && rows != 16)
+      throw Error{HT_ERR_ARG, "tile rows must be 4, 8 or 16"};
+    if (waves_in_i != 0 && waves_in_i != 1)
+      throw Error{HT_ERR_ARG, "waves_in_i must be 0 or 1"};
+    h->tuned_sweep[{level, dtype}] = {rows, waves_in_i != 0};
+  });
+}
+
+int ht_get_sweep_shape(const ht_mesh* h, int level, int dtype, int* rows,
+                       int* waves_in_i) {
+  return guard([&] {
+    if (!h || !rows || !waves_in_i) throw Error{HT_ERR_ARG, "NULL argument"};
+    check_level(h->m, level);
+    check_dtype(dtype);
+    const Shape sh = choose_shape(const_cast<ht_mesh*>(h), level, dtype, OP_JACOBI);
+    *rows = sh.J;
+    *waves_in_i = sh.in_i ? 1 : 0;
+  });
+}
+
 int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
                 int* rows, ht_stream stream) {
   return guard([&] {
     HT_DEV_PROLOGUE(level, dtype);
-    // cache: lines "<gfx arch> <level> <dtype> <cells> <stride> <rows>"
+    // cache: lines "<gfx arch> <level> <dtype> <cells> <stride> v2
+    // <apply rows> <sweep rows> <sweep waves in i>"
     hipDeviceProp_t prop;
     HT_CHECK_HIP(hipGetDeviceProperties(&prop, h->m.device));
     const CellLayout L = make_layout(level);
     std::ostringstream key;
     key << prop.gcnArchName << ' ' << level << ' ' << dtype << ' ' << h->m.nc
-        << ' ' << L.stride;
+        << ' ' << L.stride << " v2";
+    auto valid_rows = [](int J) { return J == 4 || J == 8 || J == 16; };
     if (cache_path) {
       FILE* f = std::fopen(cache_path, "r");
       if (f) {
         char line[512];
         while (std::fgets(line, sizeof line, f)) {
-          std::string ln(line);
-          const size_t sp = ln.find_last_of(' ');
-          if (sp != std::string::npos && ln.compare(0, sp, key.str()) == 0) {
-            const int J = std::atoi(ln.c_str() + sp + 1);
-            if (J == 4 || J == 8 || J == 16) {
-              h->tuned_J[{level, dtype}] = J;
-              if (rows) *rows = J;
-              std::fclose(f);
-              return;
-            }
+          const std::string ln(line), k = key.str() + ' ';
+          int J = 0, sJ = 0, sI = -1;
+          if (ln.compare(0, k.size(), k) == 0 &&
+              std::sscanf(ln.c_str() + k.size(), "%d %d %d", &J, &sJ, &sI) == 3 &&
+              valid_rows(J) && valid_rows(sJ) && (sI == 0 || sI == 1)) {
+            h->tuned_J[{level, dtype}] = J;
+            h->tuned_sweep[{level, dtype}] = {sJ, sI == 1};
+            if (rows) *rows = J;
+            std::fclose(f);
+            return;
           }
         }
         std::fclose(f);
@@ -1728,29 +1773,54 @@ int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
     const size_t bytes = level_slots(h->m, level) * esize(dtype);
     void* x = dalloc<char>(bytes);
     void* y = dalloc<char>(bytes);
+    void* bv = nullptr;
+    try {
+      bv = dalloc<char>(bytes);
+    } catch (...) {
+      (void)hipFree(x); (void)hipFree(y);
+      throw;
+    }
     hipEvent_t e0, e1;
     HT_CHECK_HIP(hipEventCreate(&e0));
     HT_CHECK_HIP(hipEventCreate(&e1));
     const bool was_profiling = h->m.profiling;
     h->m.profiling = false;
+    // mean time of five launches of `pass` after two untimed ones
+    auto time_of = [&](const std::function<void()>& pass) {
+      for (int rep = 0; rep < 2; ++rep) pass();
+      HT_CHECK_HIP(hipEventRecord(e0, s));
+      for (int rep = 0; rep < 5; ++rep) pass();
+      HT_CHECK_HIP(hipEventRecord(e1, s));
+      HT_CHECK_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      HT_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      return ms;
+    };
     int best = kDefaultJ;
-    float best_ms = 1e30f;
+    std::pair<int, bool> best_sweep{kDefaultJ, true};
     try {
+      // apply: rows per wave, waves stacked in j
+      float best_ms = 1e30f;
       for (int J : kJ) {
         h->tuned_J[{level, dtype}] = J;
-        for (int rep = 0; rep < 2; ++rep) op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s);
-        HT_CHECK_HIP(hipEventRecord(e0, s));
-        const int reps = 5;
-        for (int rep = 0; rep < reps; ++rep) op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s);
-        HT_CHECK_HIP(hipEventRecord(e1, s));
-        HT_CHECK_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        HT_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const float ms = time_of([&] { op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s); });
         if (ms < best_ms) { best_ms = ms; best = J; }
       }
+      h->tuned_J[{level, dtype}] = best;
+      // sweeps: rows per wave and wave arrangement, on the Jacobi sweep
+      // with its own right-hand side (b streams from HBM as in a solve)
+      best_ms = 1e30f;
+      for (int J : kJ)
+        for (bool in_i : {false, true}) {
+          h->tuned_sweep[{level, dtype}] = {J, in_i};
+          const float ms = time_of(
+              [&] { op_pass(h, level, dtype, OP_JACOBI, x, y, bv, 2.0 / 3.0, s); });
+          if (ms < best_ms) { best_ms = ms; best_sweep = {J, in_i}; }
+        }
     } catch (...) {
       h->m.profiling = was_profiling;
-      (void)hipFree(x); (void)hipFree(y);
+      h->tuned_sweep.erase({level, dtype});
+      (void)hipFree(x); (void)hipFree(y); (void)hipFree(bv);
       throw;
     }
     h->m.profiling = was_profiling;
@@ -1758,12 +1828,15 @@ int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
     (void)hipEventDestroy(e1);
     (void)hipFree(x);
     (void)hipFree(y);
+    (void)hipFree(bv);
     h->tuned_J[{level, dtype}] = best;
+    h->tuned_sweep[{level, dtype}] = best_sweep;
     if (rows) *rows = best;
     if (cache_path) {
       FILE* f = std::fopen(cache_path, "a");
       if (f) {
-        std::fprintf(f, "%s %d\n", key.str().c_str(), best);
+        std::fprintf(f, "%s %d %d %d\n", key.str().c_str(), best, best_sweep.first,
+                     best_sweep.second ? 1 : 0);
         std::fclose(f);
       }
     }

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   // A workgroup is kCellWaves waves on adjacent tiles of one cell, marching
   // in near lockstep on one CU: stacked in j (rows j0 .. j0 + kCellWaves J
   // - 1), each wave's halo rows are its neighbours' rows, fetched once; side
-  // by side in i (cell_waves_in_i), each row is one contiguous run.
+  // by side in i (a.waves_in_i), each row is one contiguous run.
   // XCD-aware block order: block b runs on XCD b % 8; give each XCD a
   // contiguous run of (cell, tile group) work so neighbouring groups share
   // an L2.
@@ -73,8 +73,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   // derived from it lives in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t w = wb * kCellWaves + wave;  // partial-sum slot of this wave
-  constexpr bool IN_I = cell_waves_in_i(OP);
-  const int i0 = tile.x + (IN_I ? 62 * wave : 0), j0 = tile.y + (IN_I ? 0 : wave * J);
+  const bool in_i = a.waves_in_i != 0;
+  const int i0 = tile.x + (in_i ? 62 * wave : 0), j0 = tile.y + (in_i ? 0 : wave * J);
   const int n = a.n;
   const int64_t bytes = a.stride * (int64_t)sizeof(T);
   const int64_t ostride = RESTR ? a.stride_out : a.stride;

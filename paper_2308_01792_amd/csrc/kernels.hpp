@@ -25,12 +25,10 @@ enum { kMaxInc = 128 };  // incident cells per shared primitive (checked)
 #define HT_CELL_WAVES 4
 #endif
 enum { kCellWaves = HT_CELL_WAVES };
-// Wave arrangement in a stencil workgroup.  The operations that also stream
-// b (residual, Jacobi, FP32 residual, Chebyshev step) put the waves side by
-// side in i: one workgroup then reads one run of 62 kCellWaves consecutive
-// points per row, which measured ~10% faster for them.  The others stack the
-// waves in j, so each wave's halo rows are its neighbours' rows.
-constexpr bool cell_waves_in_i(int op) {
+// The "sweep" operations stream b besides x (residual, Jacobi, FP32
+// residual, Chebyshev step); their tile shape is chosen separately from the
+// apply's.
+constexpr bool op_is_sweep(int op) {
   return op == OP_RESID || op == OP_JACOBI || op == OP_RESID32 || op == OP_CHEB;
 }
 
@@ -48,6 +46,9 @@ struct CellArgs {
   int64_t ntiles, nblocks;
   int64_t stride, off_s0, off_s1;
   int n;
+  // wave arrangement of a workgroup: 0 = stacked in j (rows j0 .. j0 +
+  // kCellWaves J - 1), 1 = side by side in i (62 kCellWaves points of J rows)
+  int waves_in_i;
   double omega, nscale; // nscale = 2^l (inverse diagonal scale)
   // restriction output (coarse level layout)
   int64_t stride_out, off_s0_out, off_s1_out;

@@ -343,11 +343,17 @@ def test_apply_every_tile_shape(name, level, rows):
         yg = torch.zeros_like(xg)
         P.m.apply(level, xg, yg)
         assert rel_err(P.from_gpu(level, yg), S.apply(x)) <= tol
-        P.m.residual(level, xg, bg, yg)
-        assert rel_err(P.from_gpu(level, yg), S.residual(x, b)) <= tol
-        P.m.smooth_jacobi(level, xg, bg, 2.0 / 3.0, 1)
-        assert rel_err(P.from_gpu(level, xg), S.jacobi(x, b, 2.0 / 3.0, 1)) <= tol
+        for in_i in (False, True):      # both workgroup arrangements
+            P.m.set_sweep_shape(level, code, rows, in_i)
+            assert P.m.sweep_shape(level, code) == (rows, in_i)
+            xg = P.to_gpu(level, x, dt)
+            P.m.residual(level, xg, bg, yg)
+            assert rel_err(P.from_gpu(level, yg), S.residual(x, b)) <= tol
+            P.m.smooth_jacobi(level, xg, bg, 2.0 / 3.0, 1)
+            assert rel_err(P.from_gpu(level, xg),
+                           S.jacobi(x, b, 2.0 / 3.0, 1)) <= tol
         P.m.set_tile_rows(level, code, 8)
+        P.m.set_sweep_shape(level, code, 4, True)
 
 
 def test_autotune_picks_a_valid_shape(tmp_path):
@@ -355,8 +361,13 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     cache = str(tmp_path / "tune.txt")
     rows = P.m.autotune(4, ht.HT_F64, cache)
     assert rows in (4, 8, 16) and P.m.tile_rows(4, ht.HT_F64) == rows
+    sweep = P.m.sweep_shape(4, ht.HT_F64)
+    assert sweep[0] in (4, 8, 16)
     P.m.set_tile_rows(4, ht.HT_F64, 4 if rows != 4 else 8)
+    P.m.set_sweep_shape(4, ht.HT_F64, 16 if sweep[0] != 16 else 8,
+                        not sweep[1])
     assert P.m.autotune(4, ht.HT_F64, cache) == rows      # from the cache
+    assert P.m.sweep_shape(4, ht.HT_F64) == sweep
     assert open(cache).read().count("\n") == 1
 
 
