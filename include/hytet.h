@@ -309,7 +309,8 @@ int ht_get_tile_rows(const ht_mesh* mesh, int level, int dtype, int* rows);
  * Chebyshev step), which also stream b: R rows per wave and the workgroup's
  * arrangement, waves_in_i = 1 for its four waves side by side in i (one
  * contiguous run of 248 points per row), 0 for stacked in j.  Default
- * R = 4, waves_in_i = 1.  Results do not depend on the shape. */
+ * R = 4, waves_in_i = 1 from level 8 on (0 below).  Results do not depend
+ * on the shape. */
 int ht_set_sweep_shape(ht_mesh* mesh, int level, int dtype, int rows,
                        int waves_in_i);
 int ht_get_sweep_shape(const ht_mesh* mesh, int level, int dtype, int* rows,

@@ -270,7 +270,8 @@ static int choose_J(ht_mesh* h, int level, int dtype) {
 // Tile shape of a stencil launch: rows per wave and wave arrangement.  The
 // apply and the restriction stack the waves in j with the tuned J; the
 // sweep operations use their own tuned shape, by default four rows with the
-// waves side by side in i (measured faster for them at the largest levels).
+// waves side by side in i where all four have points on the longest rows
+// (n >= 187, measured faster there) and stacked in j below.
 struct Shape {
   int J;
   bool in_i;
@@ -279,7 +280,7 @@ static Shape choose_shape(ht_mesh* h, int level, int dtype, int op) {
   if (!op_is_sweep(op)) return Shape{choose_J(h, level, dtype), false};
   auto it = h->tuned_sweep.find({level, dtype});
   if (it != h->tuned_sweep.end()) return Shape{it->second.first, it->second.second};
-  return Shape{kDefaultJ, true};
+  return Shape{kDefaultJ, (1 << level) >= 62 * (kCellWaves - 1) + 1};
 }
 
 // Stencil-kernel arguments over the cells of R: every per-cell array is
