@@ -13,7 +13,10 @@ library computes, straight from the paper's definitions:
   transpose as restriction, weighted Jacobi, residual, textbook V-cycle with a
   dense Cholesky coarse solve, and the solve loop;
 * ``rows``    -- single-row assembly at one micro-vertex by recursive descent
-  through the refinement, for sampled checks at levels too large to assemble.
+  through the refinement, for sampled checks at levels too large to assemble;
+* ``p2``      -- P2 (vertex + edge DoFs, Section 5.1) element matrices by exact
+  quadrature, assembly on the explicit micro-mesh with nodes keyed as the
+  next level's micro-vertices, and its single-row variant.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The GPU library never imports, links or
