@@ -153,6 +153,16 @@ int ht_slot_index(const ht_mesh* mesh, int level, int64_t cell, int i, int j,
  * that connect it to offset d (offset order in the documentation). */
 int ht_cell_stencils(const ht_mesh* mesh, int level, double* out);
 
+/* Stencil offsets of the P2 operator (ht_apply_p2) on the finer lattice:
+ * len[8] offsets per node parity p = (i & 1) | (j & 1) << 1 | (k & 1) << 2
+ * and d[8][65][3] their (di, dj, dk), sorted by (dk, dj, di). */
+int ht_p2_offsets(int* len, int* d);
+/* Class-partial P2 stencils of every cell at P2 level `level`:
+ * out[nc][8][16][65] doubles, [parity][boundary class of the fine point]
+ * [offset]; entry t is the sum of the P2 element-matrix entries of the
+ * cell's micro-tets around such a point that connect it to offset t. */
+int ht_p2_stencils(const ht_mesh* mesh, int level, double* out);
+
 /* ------------------------------------------------------- vector ops ---- */
 /* Make a vector consistent: every copy takes its owner's value. */
 int ht_sync(ht_mesh* mesh, int level, int dtype, void* v, ht_stream stream);
@@ -205,6 +215,20 @@ int ht_assemble_divkgrad(ht_mesh* mesh, int level, int dtype,
                          const void* kappa, void* rows, ht_stream stream);
 int ht_apply_stored(ht_mesh* mesh, int level, int dtype, const void* rows,
                     const void* x, void* y, ht_stream stream);
+/* y = A x for the P2 (quadratic Lagrange) Laplacian of P2 level `level`
+ * (Section 5.1: one DoF per micro-vertex and one per micro-edge, the vertex
+ * and the seven edge subgroups; element matrices of Section 5.2.1).  The P2
+ * nodes of level l are the micro-vertices of level l + 1, so x and y are
+ * vectors of level l + 1 (n_slots(l + 1) elements of `dtype`, closure
+ * layout, consistent copies): the point (i, j, k) of that level is a vertex
+ * DoF when i, j, k are all even and otherwise the DoF of the micro-edge whose
+ * midpoint it is.  y = 0 at Dirichlet nodes (those on the domain boundary);
+ * Dirichlet values of x act as data.  Needs 0 <= level and min_level <=
+ * level + 1 <= max_level (HT_ERR_LEVEL).  The library keeps the stencils of
+ * each P2 level (8 node parities x 16 boundary classes x 65 offsets per
+ * cell) after the first call.  y must not alias x. */
+int ht_apply_p2(ht_mesh* mesh, int level, int dtype, const void* x, void* y,
+                ht_stream stream);
 /* r = b - A u (0 at Dirichlet); if norm != NULL, also ||r||_2 over unique
  * non-Dirichlet micro-vertices (synchronises the stream). */
 int ht_residual(ht_mesh* mesh, int level, int dtype, const void* u,

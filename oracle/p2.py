@@ -137,9 +137,12 @@ class P2System:
         keys = np.asarray(keys, dtype=np.int64)
         if self._codec is not None:
             c = np.asarray(self._codec[0](keys))
+            shape = c.shape
+            c = c.reshape(-1)
             idx = np.searchsorted(self.codes, c)
             ok = idx < len(self.codes)
             ok[ok] = self.codes[idx[ok]] == c[ok]
+            idx, ok = idx.reshape(shape), ok.reshape(shape)
         else:
             table = {tuple(r): i for i, r in enumerate(self.keys)}
             flat = keys.reshape(-1, 8)

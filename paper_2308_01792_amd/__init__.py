@@ -20,12 +20,21 @@ from ._lib import (HT_F32, HT_F64, HT_PREC_F64, HT_PREC_MIXED,
 __all__ = ["Mesh", "Batch", "HytetError", "load", "HT_F64", "HT_F32", "HT_PREC_F64",
            "HT_PREC_MIXED", "HT_SMOOTH_JACOBI", "HT_SMOOTH_CHEBYSHEV",
            "HT_SLOT_OWNER", "HT_SLOT_GHOST",
-           "HT_SLOT_DIRICHLET", "HT_SLOT_PAD", "index_tw",
+           "HT_SLOT_DIRICHLET", "HT_SLOT_PAD", "index_tw", "p2_offsets",
            "selftest_lane_shift"]
 
 
 def load():
     return _lib.load()
+
+
+def p2_offsets():
+    """(len[8], d[8][65][3]) stencil offsets of the P2 operator per node
+    parity on the finer lattice."""
+    ln = np.empty(8, dtype=np.int32)
+    d = np.empty((8, 65, 3), dtype=np.int32)
+    check(load().ht_p2_offsets(ln.ctypes.data, d.ctypes.data))
+    return ln, d
 
 
 def index_tw(w: int, i: int, j: int, k: int) -> int:
@@ -119,6 +128,12 @@ class Mesh:
         check(load().ht_cell_stencils(self._h, level, out.ctypes.data))
         return out
 
+    def p2_stencils(self, level: int) -> np.ndarray:
+        """Class-partial P2 stencils [nc][8 parities][16 classes][65]."""
+        out = np.empty((len(self._cells), 8, 16, 65), dtype=np.float64)
+        check(load().ht_p2_stencils(self._h, level, out.ctypes.data))
+        return out
+
     # -------------------------------------------------------- device ----
     def new_vector(self, level: int, dtype=None):
         import torch
@@ -180,6 +195,14 @@ class Mesh:
         check(load().ht_apply_divkgrad(self._h, level, _dtype_code(x),
                                        _ptr(kappa), _ptr(x), _ptr(y),
                                        _stream()))
+        return y
+
+    def apply_p2(self, level: int, x, y):
+        """y = A x for the P2 Laplacian of P2 level ``level``; x and y are
+        vectors of level + 1 (the P2 nodes are that level's micro-vertices).
+        y = 0 at Dirichlet nodes."""
+        check(load().ht_apply_p2(self._h, level, _dtype_code(x), _ptr(x),
+                                 _ptr(y), _stream()))
         return y
 
     def assemble_divkgrad(self, level: int, kappa, rows=None):

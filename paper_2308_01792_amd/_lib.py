@@ -63,6 +63,8 @@ SIGNATURES = {
     "ht_slot_flags_device": (I, [P, I, P, P]),
     "ht_slot_index": (I, [P, I, L, I, I, I, C.POINTER(L)]),
     "ht_cell_stencils": (I, [P, I, P]),
+    "ht_p2_offsets": (I, [P, P]),
+    "ht_p2_stencils": (I, [P, I, P]),
     "ht_sync": (I, [P, I, I, P, P]),
     "ht_fill_dirichlet": (I, [P, I, I, P, D, P]),
     "ht_lumped_mass": (I, [P, I, I, P, P]),
@@ -71,6 +73,7 @@ SIGNATURES = {
     "ht_copy": (I, [P, I, I, P, P, P]),
     "ht_apply": (I, [P, I, I, P, P, P]),
     "ht_apply_divkgrad": (I, [P, I, I, P, P, P, P]),
+    "ht_apply_p2": (I, [P, I, I, P, P, P]),
     "ht_assemble_divkgrad": (I, [P, I, I, P, P, P]),
     "ht_apply_stored": (I, [P, I, I, P, P, P, P]),
     "ht_residual": (I, [P, I, I, P, P, P, C.POINTER(D), P]),

@@ -12,6 +12,7 @@
 #include <tuple>
 
 #include "hytet_impl.hpp"
+#include "p2.hpp"
 #include "kernels.hpp"
 #include "vcoef.hpp"
 
@@ -48,6 +49,9 @@ struct ht_mesh {
   // (level, dtype) -> (J, waves side by side in i) of the sweep operations
   std::map<std::pair<int, int>, std::pair<int, bool>> tuned_sweep;
   std::map<int, double> lambda_max;            // level -> estimate
+  // (fine level, J) -> P2 bulk tiles; fine level -> P2 face runs
+  std::map<std::pair<int, int>, std::pair<int2*, int64_t>> p2_tiles;
+  std::map<int, std::pair<int2*, int64_t>> p2_runs;
   bool capturing = false;
 };
 
@@ -206,6 +210,8 @@ void ensure_uploaded_h(ht_mesh* h) {
   m.d_w32.assign(m.max_level + 1, nullptr);
   m.d_kc64.assign(m.max_level + 1, nullptr);
   m.d_kc32.assign(m.max_level + 1, nullptr);
+  m.d_p2w64.assign(m.max_level + 1, nullptr);
+  m.d_p2w32.assign(m.max_level + 1, nullptr);
   int64_t pcap = 0;
   for (int l = m.min_level; l <= m.max_level; ++l) {
     std::vector<double> w;
@@ -450,6 +456,109 @@ static void vcoef_pass(ht_mesh* h, int level, int dtype, int mode,
 static void check_stored_level(int level, int dtype) {
   if (15 * make_layout(level).stride * (int64_t)esize(dtype) >= (int64_t)1 << 31)
     throw Error{HT_ERR_LEVEL, "stored rows of one cell exceed 2 GiB at this level"};
+}
+
+// ------------------------------------------------------------- P2 --------
+// Rows per bulk tile of the P2 kernel (the five planes of J + 4 rows and the
+// J x 2 x 3 shift sums stay in registers).
+static const int kP2J = 4;
+
+// Level-scaled P2 stencils of every cell, K / 2^l at P2 level l.
+static const void* p2_weights(ht_mesh* h, int level, int dtype) {
+  Mesh& m = h->m;
+  if (m.p2_unit.empty()) {
+    std::vector<double> u(m.nc * (int64_t)kP2PerCell);
+    parallel_for(m.nc, [&](int64_t a, int64_t b) {
+      for (int64_t c = a; c < b; ++c) {
+        double X[4][3];
+        for (int q = 0; q < 4; ++q)
+          for (int d = 0; d < 3; ++d) X[q][d] = m.xyz[3 * m.cells[c].gv[q] + d];
+        p2_cell_weights(X, u.data() + c * kP2PerCell);
+      }
+    }, 8);
+    m.p2_unit.swap(u);
+  }
+  if (!m.d_p2w64[level]) {
+    const double sc = std::ldexp(1.0, -level);
+    std::vector<double> w(m.p2_unit.size());
+    for (size_t t = 0; t < w.size(); ++t) w[t] = m.p2_unit[t] * sc;
+    std::vector<float> wf(w.begin(), w.end());
+    m.d_p2w64[level] = upload(w);
+    m.d_p2w32[level] = upload(wf);
+  }
+  return dtype == HT_F64 ? (const void*)m.d_p2w64[level] : (const void*)m.d_p2w32[level];
+}
+
+// Bulk tiles of one cell at fine n: plane k, rows j0 .. j0 + J - 1, points
+// i0 + 2 .. i0 + 125 (lanes 1 .. 62 of a wave holding i0 .. i0 + 127); only
+// tiles whose first (longest) row has a point with 1 <= i <= e - 1.
+static std::vector<int2> make_p2_tiles(int n, int J) {
+  std::vector<int2> t;
+  for (int k = 0; k <= n; ++k)
+    for (int j0 = 0; n - j0 - k >= 2; j0 += J)
+      for (int i0 = -2; i0 + 2 <= n - j0 - k - 1; i0 += kP2TileI)
+        t.push_back(make_int2(k | (j0 << 16), i0));
+  return t;
+}
+// Face runs of one cell: 64 consecutive j of plane k.
+static std::vector<int2> make_p2_runs(int n) {
+  std::vector<int2> t;
+  for (int k = 0; k <= n; ++k)
+    for (int j0 = 0; j0 + k <= n; j0 += 64) t.push_back(make_int2(k, j0));
+  return t;
+}
+
+// y = A_P2 x at P2 level `level` (vectors in the layout of level + 1): bulk
+// and face kernels, then the exchange of the finer level, which sums the
+// partial rows of shared points and zeroes Dirichlet rows.
+static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
+                    hipStream_t s) {
+  Mesh& m = h->m;
+  const int lf = level + 1;
+  const CellLayout L = make_layout(lf);
+  auto tiles = h->p2_tiles.find({lf, kP2J});
+  if (tiles == h->p2_tiles.end()) {
+    auto t = make_p2_tiles(L.n, kP2J);
+    tiles = h->p2_tiles.emplace(std::make_pair(lf, kP2J),
+                                std::make_pair(upload(t), (int64_t)t.size())).first;
+  }
+  auto runs = h->p2_runs.find(lf);
+  if (runs == h->p2_runs.end()) {
+    auto t = make_p2_runs(L.n);
+    runs = h->p2_runs.emplace(lf, std::make_pair(upload(t), (int64_t)t.size())).first;
+  }
+  P2Args a{};
+  a.x = x; a.y = y;
+  a.w = p2_weights(h, level, dtype);
+  a.tiles = tiles->second.first;
+  a.ntiles = tiles->second.second;
+  a.nblk = (a.ntiles + 3) / 4;
+  a.runs = runs->second.first;
+  a.nruns = runs->second.second;
+  a.nfblk = (a.nruns + 3) / 4;
+  a.nc = m.nc;
+  a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
+  a.n = L.n;
+  {
+    P2Args b = a;  // bulk kernel only
+    b.nfblk = 0;
+    Prof p(h, "cell_p2", s);
+    launch_p2(dtype, kP2J, b, s);
+    check_launch();
+  }
+  {
+    P2Args f = a;  // face kernel only
+    f.nblk = 0;
+    Prof p(h, "face_p2", s);
+    launch_p2(dtype, kP2J, f, s);
+    check_launch();
+  }
+  ExchArgs ea = exch_args(h, lf, y, nullptr, nullptr, 0.0, m.d_partials, full_range(m));
+  if (ea.total > 0) {
+    Prof p(h, "exchange", s);
+    launch_exchange(dtype, OP_APPLY, ea, s);
+    check_launch();
+  }
 }
 
 static void exch_only(ht_mesh* h, int level, int dtype, int op, void* v,
@@ -956,6 +1065,10 @@ int ht_mesh_destroy(ht_mesh* h) {
       for (auto* p : m.d_w32) if (p) (void)hipFree(p);
       for (auto* p : m.d_kc64) if (p) (void)hipFree(p);
       for (auto* p : m.d_kc32) if (p) (void)hipFree(p);
+      for (auto* p : m.d_p2w64) if (p) (void)hipFree(p);
+      for (auto* p : m.d_p2w32) if (p) (void)hipFree(p);
+      for (auto& kv : h->p2_tiles) (void)hipFree(kv.second.first);
+      for (auto& kv : h->p2_runs) (void)hipFree(kv.second.first);
       for (auto* list : {&m.work64, &m.work32})
         for (auto& w : *list) {
           (void)hipFree(w.u); (void)hipFree(w.b); (void)hipFree(w.t); (void)hipFree(w.d);
@@ -1055,6 +1168,35 @@ int ht_cell_stencils(const ht_mesh* h, int level, double* out) {
     std::vector<double> w;
     level_scaled_stencils(h->m, level, w);
     std::memcpy(out, w.data(), w.size() * sizeof(double));
+  });
+}
+
+int ht_p2_offsets(int* len, int* d) {
+  return guard([&] {
+    if (!len || !d) throw Error{HT_ERR_ARG, "NULL argument"};
+    for (int p = 0; p < kP2Parities; ++p) {
+      len[p] = kP2Off.len[p];
+      for (int t = 0; t < kP2MaxOffsets; ++t)
+        for (int c = 0; c < 3; ++c) d[(p * kP2MaxOffsets + t) * 3 + c] = kP2Off.d[p][t][c];
+    }
+  });
+}
+
+int ht_p2_stencils(const ht_mesh* h, int level, double* out) {
+  return guard([&] {
+    if (!h || !out) throw Error{HT_ERR_ARG, "NULL argument"};
+    if (level < 0) throw Error{HT_ERR_LEVEL, "P2 level must be >= 0"};
+    check_level(h->m, level + 1);
+    const Mesh& m = h->m;
+    const double sc = std::ldexp(1.0, -level);
+    for (int64_t c = 0; c < m.nc; ++c) {
+      double X[4][3];
+      for (int q = 0; q < 4; ++q)
+        for (int d = 0; d < 3; ++d) X[q][d] = m.xyz[3 * m.cells[c].gv[q] + d];
+      double* w = out + c * kP2PerCell;
+      p2_cell_weights(X, w);
+      for (int t = 0; t < kP2PerCell; ++t) w[t] *= sc;
+    }
   });
 }
 
@@ -1201,6 +1343,19 @@ int ht_apply_stored(ht_mesh* h, int level, int dtype, const void* rows,
     if (y == x) throw Error{HT_ERR_ARG, "y must not alias x"};
     check_stored_level(level, dtype);
     vcoef_pass(h, level, dtype, VC_STORED, nullptr, x, const_cast<void*>(rows), y, s);
+  });
+}
+
+int ht_apply_p2(ht_mesh* h, int level, int dtype, const void* x, void* y,
+                ht_stream stream) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    if (level < 0) throw Error{HT_ERR_LEVEL, "P2 level must be >= 0"};
+    HT_DEV_PROLOGUE(level + 1, dtype);
+    check_ptr(x, "x");
+    check_ptr(y, "y");
+    if (y == x) throw Error{HT_ERR_ARG, "y must not alias x"};
+    p2_pass(h, level, dtype, x, y, s);
   });
 }
 

@@ -168,6 +168,9 @@ struct Mesh {
   std::vector<float*> d_w32;
   std::vector<double*> d_kc64;            // per level [nc][36] div(k grad)
   std::vector<float*> d_kc32;             // couplings / (4 n), on first use
+  std::vector<double*> d_p2w64;           // per P2 level [nc][kP2PerCell]
+  std::vector<float*> d_p2w32;            // level-scaled P2 stencils, on first use
+  std::vector<double> p2_unit;            // [nc][kP2PerCell] unit scale (host)
   double* d_partials = nullptr;           // norm partial sums
   int64_t partials_cap = 0;
   double* d_scalar = nullptr;             // reduced scalars

@@ -97,4 +97,19 @@ HT_HD void stencil_offset(int d, int& di, int& dj, int& dk) {
 }
 enum { kNumOffsets = 15, kNumClasses = 16 };
 
+// Micro-cell shapes of a regularly refined cell.  Recursive application of
+// eq. (bey) produces, on every level, translated copies of six shapes; below,
+// each is given by the index offsets of its four vertices (in the vertex order
+// of the eq. (bey) children) from its base point b.  Valid bases are
+// b >= 0 with |b| <= n-1 (first), n-3 (second) and n-2 (the other four),
+// i.e. polytope widths 2^l, 2^l-2 and 2^l-1 of the paper's cell subgroups.
+constexpr int kShapeOffsets[6][4][3] = {
+    {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+    {{1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}},
+    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 0, 1}},
+    {{1, 0, 0}, {0, 1, 0}, {1, 1, 0}, {1, 0, 1}},
+    {{0, 1, 0}, {0, 0, 1}, {1, 0, 1}, {0, 1, 1}},
+    {{0, 1, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}},
+};
+
 }  // namespace ht

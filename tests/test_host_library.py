@@ -213,3 +213,45 @@ def test_batch_create_and_errors(lib):
     o.cyc.coarse_level = min(p.level for p in probs) + 1
     assert lib.ht_batch_solve(b._h, C.byref(o), fake, fake, st, None) == _lib.HT_ERR_LEVEL
     b.close()
+
+
+P2_CASES = [("ref_tet", 0), ("ref_tet", 2), ("kuhn_211", 1),
+            ("jittered_222", 1), ("slab_3_11", 1), ("slab_1_1", 1)]
+
+
+@pytest.mark.parametrize("name,level", P2_CASES)
+def test_p2_stencils_assemble_to_oracle_matrix(lib, name, level):
+    """Sum over all slot copies of the library's class-partial P2 stencils,
+    placed with the library's keys of level + 1, equals the oracle's P2
+    matrix assembled element by element on the explicit micro-mesh."""
+    import scipy.sparse as sp
+    from oracle.p2 import P2System
+    from oracle.refine import keys_of
+    xyz, cells = mesh_by_name(name)
+    S = P2System(xyz, cells, level)
+    fine = level + 1
+    m = ht.Mesh(xyz, cells, fine, fine)
+    n = 2 ** fine
+    W = m.p2_stencils(level)
+    ln, D = ht.p2_offsets()
+    assert list(ln) == [65, 27, 19, 27, 27, 19, 27, 19]
+    keys, flags = m.keys(fine)
+    loc = _slot_local_index(m, fine, keys, flags)
+    rows, cols, vals = [], [], []
+    for s, (c, i, j, k) in loc.items():
+        cls = (i == 0) | ((j == 0) << 1) | ((k == 0) << 2) | ((i + j + k == n) << 3)
+        par = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2)
+        r = S.index_of(keys[s])
+        for t in range(ln[par]):
+            w = W[c, par, cls, t]
+            if w == 0.0:
+                continue
+            ii, jj, kk = i + D[par, t, 0], j + D[par, t, 1], k + D[par, t, 2]
+            assert min(ii, jj, kk) >= 0 and ii + jj + kk <= n
+            nk = keys_of(cells[c], np.array([n - ii - jj - kk, ii, jj, kk]))
+            rows.append(r)
+            cols.append(S.index_of(nk))
+            vals.append(w)
+    N = S.num_nodes
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+    assert abs(A - S.A).max() <= 1e-13 * abs(S.A).max()
