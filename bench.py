@@ -32,6 +32,11 @@ DIVKGRAD_BYTES_PER_DOF = {"f64": 24.0, "f32": 12.0}
 DIVKGRAD_FLOPS_PER_DOF = 24 * 10 + 14
 # stored rows: read 15 entries and x, write y per interior DoF
 STORED_BYTES_PER_DOF = {"f64": 17 * 8.0, "f32": 17 * 4.0}
+# P2 apply at P2 level L - 1 (its nodes are the level-L micro-vertices): read
+# x, write y per DoF; 230 stencil entries over the 8 node parities, i.e.
+# 28.75 multiply-adds per DoF on average.
+P2_BYTES_PER_DOF = {"f64": 16.0, "f32": 8.0}
+P2_FLOPS_PER_DOF = 2 * 230 / 8
 FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
 
 
@@ -52,6 +57,7 @@ def parse():
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-divkgrad", action="store_true")
     p.add_argument("--no-stored", action="store_true")
+    p.add_argument("--no-p2", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run 3 plain device copies of one level vector "
                         "(counter calibration for rocprofv3 --pmc)")
@@ -255,6 +261,47 @@ def cpu_baseline(level: int, budget_s: float):
                       f"in {el:.1f} s (assembly {setup:.1f} s untimed)"}
 
 
+def p2_leg(mesh, L, x, ndof, args, stream):
+    """P2 apply at P2 level L - 1 on the same mesh: its nodes are the level-L
+    micro-vertices, so the vectors and the DoF count are those of level L.
+    Bulk kernel (rows' inner points), face kernel (points on the faces
+    i = 0 and i = n - j - k) and exchange, FP64 and FP32."""
+    import torch
+    res = {"p2_level": L - 1}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        x_ = x.to(dt)
+        y_ = torch.zeros_like(x_)
+        for _ in range(args.warmup):
+            mesh.apply_p2(L - 1, x_, y_)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            mesh.apply_p2(L - 1, x_, y_)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        mesh.profile(True)
+        mesh.profile_reset()
+        for _ in range(args.steps):
+            mesh.apply_p2(L - 1, x_, y_)
+        torch.cuda.synchronize()
+        kern = {k: mesh.profile_query(k) for k in ("cell_p2", "face_p2", "exchange")}
+        mesh.profile(False)
+        kern = {k: v[0] / v[1] for k, v in kern.items() if v[1] > 0}
+        gbs = P2_BYTES_PER_DOF[name] * ndof / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 4), "gdofs": round(ndof / (ms * 1e-3) / 1e9, 3),
+                     "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
+                     "algorithmic_gbs": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "tflops": round(P2_FLOPS_PER_DOF * ndof / (ms * 1e-3) / 1e12, 2)}
+        log(f"P2 apply {name} (P2 level {L - 1}): {ms:.3f} ms/step "
+            f"({res[name]['gdofs']:.1f} GDoF/s, {gbs:.0f} GB/s), kernels " +
+            ", ".join(f"{k} {v:.3f} ms" for k, v in kern.items()))
+        del x_, y_
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -388,6 +435,10 @@ def main():
     # ---------------- variable coefficient: div(k grad) apply -------------
     if not args.no_divkgrad:
         out["divkgrad_apply"] = divkgrad_leg(mesh, L, x, ndof, args, stream)
+
+    # ---------------- P2: vertex + edge DoFs ------------------------------
+    if not args.no_p2:
+        out["p2_apply"] = p2_leg(mesh, L, x, ndof, args, stream)
 
     # ---------------- solves to 1e-10 --------------------------------------
     if not args.no_solve:

@@ -500,11 +500,18 @@ static std::vector<int2> make_p2_tiles(int n, int J) {
         t.push_back(make_int2(k | (j0 << 16), i0));
   return t;
 }
-// Face runs of one cell: 64 consecutive j of plane k.
+// Face runs of one cell: (k | side << 16 | s << 17, j0) for the points
+// j = j0 + 2 lane + s of plane k on face i = 0 (side 0, j + k <= n) or on
+// the slanted face (side 1, j + k <= n - 1).
 static std::vector<int2> make_p2_runs(int n) {
   std::vector<int2> t;
   for (int k = 0; k <= n; ++k)
-    for (int j0 = 0; j0 + k <= n; j0 += 64) t.push_back(make_int2(k, j0));
+    for (int side = 0; side < 2; ++side) {
+      const int jmax = side == 0 ? n - k : n - k - 1;
+      for (int j0 = 0; j0 <= jmax; j0 += 128)
+        for (int s = 0; s < 2 && j0 + s <= jmax; ++s)
+          t.push_back(make_int2(k | (side << 16) | (s << 17), j0));
+    }
   return t;
 }
 

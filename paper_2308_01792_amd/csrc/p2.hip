@@ -12,9 +12,9 @@
 // M block); their boundary class depends only on j == 0 and k == 0, which
 // are uniform over a row.
 //
-// Face kernel: the points of the faces i = 0 and i = n - j - k, one thread
-// each, with the weights of their own boundary class and a gather over the
-// stencil of their parity.
+// Face kernel: the points of the faces i = 0 and i = n - j - k, one lane
+// each, waves of one node parity, with the weights of their own boundary
+// class and a gather over the unrolled stencil of their parity.
 //
 // Points on the cell surface get the cell's partial row; the ghost exchange
 // completes them and zeroes Dirichlet rows.
@@ -142,37 +142,85 @@ __global__ __launch_bounds__(256) void k_p2_bulk(P2Args a) {
   }
 }
 
+// Points of one face of one cell for one parity class: SIDE 0 is the face
+// i = 0 (S0), SIDE 1 the face i = n - j - k (S1, points with i >= 1).  The
+// stencil is unrolled at compile time; entries that always have zero weight
+// on that face (di < 0 on i = 0, di + dj + dk > 0 on the slanted face) are
+// dropped, so every remaining neighbour lies inside the closure whenever its
+// row exists.
+template <typename T, int P, int SIDE>
+__device__ __forceinline__ void p2_face_points(const P2Args& a, int64_t cell,
+                                               int k, int j) {
+  const int n = a.n;
+  const bool valid = SIDE == 0 ? j + k <= n : j + k <= n - 1;
+  const int i = SIDE == 0 ? 0 : n - j - k;
+  const int64_t bytes = a.stride * (int64_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
+  const T* wp = (const T*)a.w + cell * (int64_t)kP2PerCell +
+                (P * kNumClasses + point_class(n, i, j, k)) * kP2MaxOffsets;
+  T acc = 0;
+  static_for<kP2Off.len[P]>([&](auto TT) {
+    constexpr int t = decltype(TT)::value;
+    constexpr int di = kP2Off.d[P][t][0], dj = kP2Off.d[P][t][1], dk = kP2Off.d[P][t][2];
+    if constexpr ((SIDE == 0 && di >= 0) || (SIDE == 1 && di + dj + dk <= 0)) {
+      const int ii = i + di, jj = j + dj, kk = k + dk;
+      const bool ok = valid && jj >= 0 && kk >= 0 && ii >= 0 && ii + jj + kk <= n;
+      // closure offset: face i = 0, slanted face, or M block (index.hpp)
+      int32_t off;
+      if constexpr (SIDE == 0 && di == 0) {
+        off = (int32_t)a.off_s0 + t2w32(n + 1, jj, kk);
+      } else if constexpr (SIDE == 1 && di + dj + dk == 0) {
+        // on the slanted face too; a one-point row (i = 0) lies in S0
+        off = ii == 0 ? (int32_t)a.off_s0 + t2w32(n + 1, jj, kk)
+                      : (int32_t)a.off_s1 + t2w32(n, jj, kk);
+      } else {
+        const int w = n - 1 - kk;
+        const int32_t m = tet32(n - 1) - tet32(w) + tri32(w) - tri32(w - jj) + ii - 1;
+        const int32_t s1 = (int32_t)a.off_s1 + t2w32(n, jj, kk);
+        const int32_t s0 = (int32_t)a.off_s0 + t2w32(n + 1, jj, kk);
+        off = ii == 0 ? s0 : (ii + jj + kk == n ? s1 : m);
+      }
+      T xv;
+      bload(xv, rx, ok ? (unsigned)off * (unsigned)sizeof(T) : HT_OOB);
+      acc += wp[t] * xv;
+    }
+  });
+  if (valid) {
+    T* y = (T*)a.y + cell * a.stride;
+    y[SIDE == 0 ? a.off_s0 + t2w32(n + 1, j, k) : a.off_s1 + t2w32(n, j, k)] = acc;
+  }
+}
+
+template <typename T, int SIDE>
+__device__ __forceinline__ void p2_face_run(const P2Args& a, int64_t cell, int k,
+                                            int j, int P) {
+  switch (P) {
+    case 0: p2_face_points<T, 0, SIDE>(a, cell, k, j); break;
+    case 1: p2_face_points<T, 1, SIDE>(a, cell, k, j); break;
+    case 2: p2_face_points<T, 2, SIDE>(a, cell, k, j); break;
+    case 3: p2_face_points<T, 3, SIDE>(a, cell, k, j); break;
+    case 4: p2_face_points<T, 4, SIDE>(a, cell, k, j); break;
+    case 5: p2_face_points<T, 5, SIDE>(a, cell, k, j); break;
+    case 6: p2_face_points<T, 6, SIDE>(a, cell, k, j); break;
+    default: p2_face_points<T, 7, SIDE>(a, cell, k, j); break;
+  }
+}
+
+// One wave per run: face SIDE, plane k, lanes j = j0 + 2 lane + s (j0 a
+// multiple of 128), so the node parity is uniform over the wave.
 template <typename T>
 __global__ __launch_bounds__(256) void k_p2_face(P2Args a) {
   const int64_t wb = xcd_block(a.nc * a.nfblk);
   if (wb >= a.nc * a.nfblk) return;
   const int64_t cell = wb / a.nfblk;
-  const int64_t rix = (wb % a.nfblk) * 4 + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t rix = (wb % a.nfblk) * 4 + wave;
   if (rix >= a.nruns) return;
   const int2 run = a.runs[rix];
-  const int n = a.n, k = run.x, j = run.y + (int)(threadIdx.x & 63);
-  if (j + k > n) return;
-  const Lay L{n, a.stride, a.off_s0, a.off_s1};
-  const T* x = (const T*)a.x + cell * a.stride;
-  T* y = (T*)a.y + cell * a.stride;
-  const T* wc = (const T*)a.w + cell * (int64_t)kP2PerCell;
-  for (int side = 0; side < 2; ++side) {
-    const int i = side == 0 ? 0 : n - j - k;
-    if (side == 1 && i == 0) break;  // a one-point row lies in face i = 0
-    const int P = (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
-    const T* wp = wc + (P * kNumClasses + point_class(n, i, j, k)) * kP2MaxOffsets;
-    T acc = 0;
-    const int len = kP2OffDev.len[P];
-    for (int t = 0; t < len; ++t) {
-      const T wt = wp[t];
-      if (wt == T(0)) continue;
-      const int ii = i + kP2OffDev.d[P][t][0], jj = j + kP2OffDev.d[P][t][1],
-                kk = k + kP2OffDev.d[P][t][2];
-      if (ii < 0 || jj < 0 || kk < 0 || ii + jj + kk > n) continue;
-      acc += wt * x[slot_of(L, ii, jj, kk)];
-    }
-    y[slot_of(L, i, j, k)] = acc;
-  }
+  const int k = run.x & 0xffff, side = (run.x >> 16) & 1, s = run.x >> 17;
+  const int j = run.y + 2 * (int)(threadIdx.x & 63) + s;
+  if (side == 0) p2_face_run<T, 0>(a, cell, k, j, (s << 1) | ((k & 1) << 2));
+  else p2_face_run<T, 1>(a, cell, k, j, ((s + k) & 1) | (s << 1) | ((k & 1) << 2));
 }
 
 template <typename T>

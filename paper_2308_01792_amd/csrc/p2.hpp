@@ -114,8 +114,9 @@ enum { kP2PerCell = kP2Parities * kNumClasses * kP2MaxOffsets };
 void p2_cell_weights(const double X[4][3], double* w /* [kP2PerCell] */);
 
 // Work of one cell for the bulk kernel: tiles (k | j0 << 16, i0) of J rows x
-// 124 points; for the face kernel: (k, j0) runs of 64 points of the faces
-// i = 0 and i = n - j - k.
+// 124 points; for the face kernel: runs (k | side << 16 | s << 17, j0) of the
+// 64 points j = j0 + 2 lane + s of face i = 0 (side 0) or i = n - j - k
+// (side 1) in plane k.
 struct P2Args {
   const void* x;
   void* y;
