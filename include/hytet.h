@@ -229,6 +229,27 @@ int ht_apply_stored(ht_mesh* mesh, int level, int dtype, const void* rows,
  * cell) after the first call.  y must not alias x. */
 int ht_apply_p2(ht_mesh* mesh, int level, int dtype, const void* x, void* y,
                 ht_stream stream);
+/* Layouts of the per-cell subgroup arrays of ht_p2_pack / ht_p2_unpack. */
+enum { HT_LAYOUT_AOS = 0, HT_LAYOUT_SOA = 1 };
+/* Convert P2 functions with m components per node (1 <= m <= 64) between
+ * the library's lattice layout and the paper's subgroup arrays (subgroup
+ * table; Section 4, AoS and SoA linearisations).
+ * `lattice`: m vectors of level + 1 (n_slots(level + 1) elements each, back
+ * to back).  `arrays`: per cell, in cell order, m * N_tet(2^(level+1) + 1)
+ * elements: the subgroups vertex, x, y, z, xy, xz, yz, xyz one after the
+ * other, subgroup g holding the N_tet(w_g) micro-primitives of its polytope
+ * (widths 2^level + 1, 2^level six times, 2^level - 1) in t_w order, each
+ * with its m DoFs: element m t_w + d (HT_LAYOUT_AOS) or d N_tet(w_g) + t_w
+ * (HT_LAYOUT_SOA).  Subgroup g at index (i, j, k) is the point
+ * 2 (i, j, k) + s_g of level + 1, s_g = (0,0,0), (1,0,0), (0,1,0), (0,0,1),
+ * (1,1,0), (1,0,1), (0,1,1), (1,1,1): the micro-vertex, or the midpoint of
+ * the micro-edge of that direction based at (i, j, k).  ht_p2_unpack writes
+ * every copy of a shared node from its cell's arrays and leaves padding
+ * slots alone.  HT_ERR_LEVEL / HT_ERR_ARG as for ht_apply_p2. */
+int ht_p2_pack(ht_mesh* mesh, int level, int dtype, int m, int layout,
+               const void* lattice, void* arrays, ht_stream stream);
+int ht_p2_unpack(ht_mesh* mesh, int level, int dtype, int m, int layout,
+                 const void* arrays, void* lattice, ht_stream stream);
 /* r = b - A u (0 at Dirichlet); if norm != NULL, also ||r||_2 over unique
  * non-Dirichlet micro-vertices (synchronises the stream). */
 int ht_residual(ht_mesh* mesh, int level, int dtype, const void* u,

@@ -230,3 +230,51 @@ def p2_row_at(macro_xyz, cells, level: int, key: np.ndarray):
     vals = np.array([acc[tuple(k)] for k in nbr])
     dirichlet = any(v == 1 for v in face_count.values())
     return nbr, vals, dirichlet
+
+
+# ------------------------------------------------- subgroup arrays (AoS/SoA) --
+# The micro-primitive subgroups of a P2 function on one cell (subgroup table):
+# the micro-vertices (width 2^l + 1) and the seven micro-edge subgroups x, y,
+# z, xy, xz, yz (width 2^l) and xyz (width 2^l - 1).  Subgroup g at index
+# (i, j, k) is the node at fine coordinates 2 (i, j, k) + SUBGROUP_SHIFT[g]:
+# the micro-vertex itself, or the midpoint of the micro-edge of that
+# direction based there (x: (i,j,k)-(i+1,j,k); xy: (i+1,j,k)-(i,j+1,k); xyz:
+# (i,j+1,k)-(i+1,j,k+1), the refinement's inner diagonal).
+SUBGROUPS = ("vertex", "x", "y", "z", "xy", "xz", "yz", "xyz")
+SUBGROUP_SHIFT = ((0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1),
+                  (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1))
+
+
+def subgroup_width(g: int, level: int) -> int:
+    n = 2 ** level
+    return n + 1 if g == 0 else (n - 1 if g == 7 else n)
+
+
+def subgroup_arrays(cells, level: int, value_of_keys, m: int, layout: str):
+    """Pack a P2 function with m components into the paper's per-cell arrays.
+
+    ``value_of_keys(keys [p, 8]) -> [p, m]`` gives the components at nodes
+    identified by their level-(level + 1) keys.  For every cell, in cell
+    order, and every subgroup in SUBGROUPS order, the structures of the
+    subgroup's micro-primitives are visited in the loop order k, j, i of the
+    index polytope, which is the order of t_w (Section 4); the subgroup array
+    holds them either as structures one after the other (AoS: element
+    m t_w + d) or component by component (SoA: element d N_tet(w) + t_w).
+    Returns one flat array: cells, then subgroups, each of m N_tet(w)."""
+    assert layout in ("aos", "soa")
+    n2 = 2 ** (level + 1)
+    out = []
+    for c in range(len(cells)):
+        cid = np.asarray(cells[c])
+        for g in range(8):
+            w = subgroup_width(g, level)
+            pts = [(i, j, k) for k in range(w) for j in range(w - k)
+                   for i in range(w - k - j)]
+            if not pts:
+                continue
+            sh = np.array(SUBGROUP_SHIFT[g])
+            fine = 2 * np.array(pts) + sh                       # [p, 3]
+            wts = np.concatenate([n2 - fine.sum(axis=1, keepdims=True), fine], axis=1)
+            vals = np.asarray(value_of_keys(keys_of(cid, wts)))  # [p, m]
+            out.append(vals.reshape(-1) if layout == "aos" else vals.T.reshape(-1))
+    return np.concatenate(out)

@@ -28,6 +28,12 @@ def load():
     return _lib.load()
 
 
+def _layout_code(layout: str) -> int:
+    if layout not in ("aos", "soa"):
+        raise ValueError("layout must be 'aos' or 'soa'")
+    return 0 if layout == "aos" else 1
+
+
 def p2_offsets():
     """(len[8], d[8][65][3]) stencil offsets of the P2 operator per node
     parity on the finer lattice."""
@@ -204,6 +210,29 @@ class Mesh:
         check(load().ht_apply_p2(self._h, level, _dtype_code(x), _ptr(x),
                                  _ptr(y), _stream()))
         return y
+
+    def p2_pack(self, level: int, lattice, m: int = 1, layout: str = "aos",
+                out=None):
+        """Per-cell subgroup arrays of m P2 functions given as m vectors of
+        level + 1 back to back in ``lattice`` (see ht_p2_pack)."""
+        import torch
+        n = 2 ** (level + 1) + 1
+        size = len(self._cells) * m * (n * (n + 1) * (n + 2) // 6)
+        if out is None:
+            out = torch.empty(size, dtype=lattice.dtype, device=lattice.device)
+        check(load().ht_p2_pack(self._h, level, _dtype_code(lattice), m,
+                                _layout_code(layout), _ptr(lattice), _ptr(out),
+                                _stream()))
+        return out
+
+    def p2_unpack(self, level: int, arrays, lattice, m: int = 1,
+                  layout: str = "aos"):
+        """Inverse of p2_pack: write every copy of every node of ``lattice``
+        (m vectors of level + 1) from the subgroup arrays."""
+        check(load().ht_p2_unpack(self._h, level, _dtype_code(arrays), m,
+                                  _layout_code(layout), _ptr(arrays),
+                                  _ptr(lattice), _stream()))
+        return lattice
 
     def assemble_divkgrad(self, level: int, kappa, rows=None):
         """The 15 row entries of A_k per slot, [cell][offset][closure slot]

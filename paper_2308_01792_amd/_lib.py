@@ -74,6 +74,8 @@ SIGNATURES = {
     "ht_apply": (I, [P, I, I, P, P, P]),
     "ht_apply_divkgrad": (I, [P, I, I, P, P, P, P]),
     "ht_apply_p2": (I, [P, I, I, P, P, P]),
+    "ht_p2_pack": (I, [P, I, I, I, I, P, P, P]),
+    "ht_p2_unpack": (I, [P, I, I, I, I, P, P, P]),
     "ht_assemble_divkgrad": (I, [P, I, I, P, P, P]),
     "ht_apply_stored": (I, [P, I, I, P, P, P, P]),
     "ht_residual": (I, [P, I, I, P, P, P, C.POINTER(D), P]),

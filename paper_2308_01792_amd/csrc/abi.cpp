@@ -52,6 +52,8 @@ struct ht_mesh {
   // (fine level, J) -> P2 bulk tiles; fine level -> P2 face runs
   std::map<std::pair<int, int>, std::pair<int2*, int64_t>> p2_tiles;
   std::map<int, std::pair<int2*, int64_t>> p2_runs;
+  // P2 level -> subgroup rows (g, k, j, element offset) of one cell
+  std::map<int, std::pair<int4*, int64_t>> p2_pack_rows;
   bool capturing = false;
 };
 
@@ -568,6 +570,51 @@ static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   }
 }
 
+// Subgroup rows of one cell at P2 level `level`: (g, k, j, offset of subgroup
+// g's array for one component), subgroups in the order vertex, x, y, z, xy,
+// xz, yz, xyz with widths 2^l + 1, 2^l (six times), 2^l - 1.
+static std::vector<int4> make_p2_pack_rows(int level) {
+  std::vector<int4> t;
+  const int n = 1 << level;
+  int64_t off = 0;
+  for (int g = 0; g < 8; ++g) {
+    const int w = g == 0 ? n + 1 : (g == 7 ? n - 1 : n);
+    for (int k = 0; k < w; ++k)
+      for (int j = 0; j < w - k; ++j) t.push_back(make_int4(g, k, j, (int)off));
+    off += n_tet(w);
+  }
+  return t;
+}
+
+static void p2_pack_pass(ht_mesh* h, int level, int dtype, int m, int layout,
+                         const void* lattice, void* arrays, bool unpack,
+                         hipStream_t s) {
+  Mesh& m_ = h->m;
+  const int lf = level + 1;
+  const CellLayout L = make_layout(lf);
+  auto rows = h->p2_pack_rows.find(level);
+  if (rows == h->p2_pack_rows.end()) {
+    auto t = make_p2_pack_rows(level);
+    rows = h->p2_pack_rows.emplace(level, std::make_pair(upload(t), (int64_t)t.size())).first;
+  }
+  P2PackArgs a{};
+  a.lattice = lattice;
+  a.arrays = arrays;
+  a.rows = rows->second.first;
+  a.nrows = rows->second.second;
+  a.nc = m_.nc;
+  a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
+  a.comp_stride = level_slots(m_, lf);
+  a.cell_elems = (int64_t)m * n_tet(L.n + 1);
+  a.n = L.n;
+  a.m = m;
+  a.soa = layout == HT_LAYOUT_SOA;
+  a.unpack = unpack;
+  Prof p(h, unpack ? "p2_unpack" : "p2_pack", s);
+  launch_p2_pack(dtype, a, s);
+  check_launch();
+}
+
 static void exch_only(ht_mesh* h, int level, int dtype, int op, void* v,
                       double fill, hipStream_t s) {
   ExchArgs ea = exch_args(h, level, v, nullptr, nullptr, 0.0, h->m.d_partials,
@@ -1076,6 +1123,7 @@ int ht_mesh_destroy(ht_mesh* h) {
       for (auto* p : m.d_p2w32) if (p) (void)hipFree(p);
       for (auto& kv : h->p2_tiles) (void)hipFree(kv.second.first);
       for (auto& kv : h->p2_runs) (void)hipFree(kv.second.first);
+      for (auto& kv : h->p2_pack_rows) (void)hipFree(kv.second.first);
       for (auto* list : {&m.work64, &m.work32})
         for (auto& w : *list) {
           (void)hipFree(w.u); (void)hipFree(w.b); (void)hipFree(w.t); (void)hipFree(w.d);
@@ -1363,6 +1411,36 @@ int ht_apply_p2(ht_mesh* h, int level, int dtype, const void* x, void* y,
     check_ptr(y, "y");
     if (y == x) throw Error{HT_ERR_ARG, "y must not alias x"};
     p2_pass(h, level, dtype, x, y, s);
+  });
+}
+
+static void check_pack(ht_mesh* h, int level, int m, int layout) {
+  if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+  if (level < 0) throw Error{HT_ERR_LEVEL, "P2 level must be >= 0"};
+  if (m < 1 || m > 64) throw Error{HT_ERR_ARG, "components per node must be 1 .. 64"};
+  if (layout != HT_LAYOUT_AOS && layout != HT_LAYOUT_SOA)
+    throw Error{HT_ERR_ARG, "layout must be HT_LAYOUT_AOS or HT_LAYOUT_SOA"};
+}
+
+int ht_p2_pack(ht_mesh* h, int level, int dtype, int m, int layout,
+               const void* lattice, void* arrays, ht_stream stream) {
+  return guard([&] {
+    check_pack(h, level, m, layout);
+    HT_DEV_PROLOGUE(level + 1, dtype);
+    check_ptr(lattice, "lattice");
+    check_ptr(arrays, "arrays");
+    p2_pack_pass(h, level, dtype, m, layout, lattice, arrays, false, s);
+  });
+}
+
+int ht_p2_unpack(ht_mesh* h, int level, int dtype, int m, int layout,
+                 const void* arrays, void* lattice, ht_stream stream) {
+  return guard([&] {
+    check_pack(h, level, m, layout);
+    HT_DEV_PROLOGUE(level + 1, dtype);
+    check_ptr(lattice, "lattice");
+    check_ptr(arrays, "arrays");
+    p2_pack_pass(h, level, dtype, m, layout, lattice, const_cast<void*>(arrays), true, s);
   });
 }
 

@@ -241,7 +241,47 @@ void launch_p2_t(int J, const P2Args& a, hipStream_t s) {
   }
 }
 
+// One wave per subgroup row (g, k, j) of one cell; lanes walk i.
+template <typename T>
+__global__ __launch_bounds__(256) void k_p2_pack(P2PackArgs a) {
+  const int64_t nblk = (a.nrows + 3) / 4;
+  const int64_t b = blockIdx.x;
+  if (b >= a.nc * nblk) return;
+  const int64_t cell = b / nblk;
+  const int64_t r = (b % nblk) * 4 + (threadIdx.x >> 6);
+  if (r >= a.nrows) return;
+  const int4 row = a.rows[r];
+  const int g = row.x, k = row.y, j = row.z;
+  const int nco = a.n / 2;
+  const int w = g == 0 ? nco + 1 : (g == 7 ? nco - 1 : nco);
+  const int sx = (g == 1 || g == 4 || g == 5 || g == 7);
+  const int sy = (g == 2 || g == 4 || g == 6 || g == 7);
+  const int sz = (g == 3 || g == 5 || g == 6 || g == 7);
+  const int64_t N = tet32(w);
+  const Lay L{a.n, a.stride, a.off_s0, a.off_s1};
+  const int64_t base = cell * a.cell_elems + (int64_t)a.m * row.w;
+  T* lat = (T*)a.lattice;
+  T* arr = (T*)a.arrays;
+  for (int i = threadIdx.x & 63; i < w - k - j; i += 64) {
+    const int64_t slot = cell * a.stride + slot_of(L, 2 * i + sx, 2 * j + sy, 2 * k + sz);
+    const int64_t t = tw32(w, i, j, k);
+    for (int d = 0; d < a.m; ++d) {
+      const int64_t e = base + (a.soa ? d * N + t : (int64_t)a.m * t + d);
+      const int64_t q = d * a.comp_stride + slot;
+      if (a.unpack) lat[q] = arr[e];
+      else arr[e] = lat[q];
+    }
+  }
+}
+
 }  // namespace
+
+void launch_p2_pack(int dtype, const P2PackArgs& a, hipStream_t s) {
+  const int64_t nb = a.nc * ((a.nrows + 3) / 4);
+  if (nb <= 0) return;
+  if (dtype == HT_F64) hipLaunchKernelGGL((k_p2_pack<double>), dim3((unsigned)nb), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_p2_pack<float>), dim3((unsigned)nb), dim3(256), 0, s, a);
+}
 
 void launch_p2(int dtype, int J, const P2Args& a, hipStream_t s) {
   if (!a.x || !a.y || !a.w) throw Error{HT_ERR_ARG, "P2 kernel needs x, y and the weights"};

@@ -133,4 +133,20 @@ enum { kP2TileI = 124 };
 
 void launch_p2(int dtype, int J, const P2Args& a, hipStream_t s);
 
+// Conversion between the lattice layout and the paper's per-cell subgroup
+// arrays (subgroup table, Section 4 AoS / SoA layouts).  Subgroup g (vertex,
+// x, y, z, xy, xz, yz, xyz) at index (i, j, k) of its polytope of width w_g
+// (2^l + 1, 2^l six times, 2^l - 1) is the fine point 2 (i, j, k) + shift_g.
+struct P2PackArgs {
+  const void* lattice;    // m vectors of the fine level, comp_stride apart
+  void* arrays;           // [nc][m * N_tet(2^(l+1) + 1)]
+  const int4* rows;       // (g, k, j, element offset of subgroup g for m = 1)
+  int64_t nrows, nc;
+  int64_t stride, off_s0, off_s1;
+  int64_t comp_stride, cell_elems;
+  int n;                  // fine intervals per macro-edge
+  int m, soa, unpack;
+};
+void launch_p2_pack(int dtype, const P2PackArgs& a, hipStream_t s);
+
 }  // namespace ht

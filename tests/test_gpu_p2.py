@@ -7,7 +7,8 @@ bulk tiles in i with a ragged tail, and rows of every length).  Full size
 sampled points against the oracle's single-row assembly, plus properties
 that hold at any size: affine fields are annihilated on interior nodes, the
 interior operator is symmetric, and a quadratic field gives the oracle's
-load vector at its interior nodes.
+load vector at its interior nodes.  The subgroup arrays (AoS / SoA) of
+ht_p2_pack against the oracle's, bit-exact, and ht_p2_unpack as its inverse.
 """
 import numpy as np
 import pytest
@@ -229,4 +230,29 @@ def test_p2_quadratic_gives_the_load(name, level):
     I = p.S.interior
     assert np.abs(got[I] - f * p.S.load[I]).max() <= \
         1e-11 * np.abs(p.S.A).max() * np.abs(u).max()
+    p.m.close()
+
+
+# ------------------------------------------------------ subgroup arrays --
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+@pytest.mark.parametrize("name,level,m,dtype", [
+    ("jittered_222", 2, 3, torch.float64), ("ref_tet", 3, 1, torch.float64),
+    ("slab_3_11", 1, 2, torch.float32), ("ref_tet", 0, 2, torch.float64)])
+def test_p2_subgroup_arrays_match_oracle(name, level, m, dtype, layout):
+    """ht_p2_pack against the oracle's per-cell subgroup arrays (t_w order,
+    AoS / SoA), bit-exact; ht_p2_unpack restores every non-padding slot."""
+    from oracle.p2 import subgroup_arrays
+    p = P2Pair(name, level)
+    vals = np.random.default_rng(8).uniform(-1, 1, (p.S.num_nodes, m))
+    vals = vals.astype(np.float32).astype(np.float64) if dtype == torch.float32 else vals
+    lat = torch.cat([p.to_gpu(vals[:, d], dtype) for d in range(m)])
+    arr = p.m.p2_pack(level, lat, m, layout)
+    torch.cuda.synchronize()
+    want = subgroup_arrays(p.cells, level, lambda keys: vals[p.S.index_of(keys)],
+                           m, layout)
+    assert np.array_equal(arr.double().cpu().numpy(), want)
+    back = torch.full_like(lat, float("nan"))
+    p.m.p2_unpack(level, arr, back, m, layout)
+    real = torch.as_tensor(np.tile(p.idx >= 0, m), device="cuda")
+    assert torch.equal(back[real], lat[real])
     p.m.close()

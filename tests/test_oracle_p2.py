@@ -144,3 +144,60 @@ def test_row_oracle_matches_assembly(name, level):
         row[S.index_of(nbr)] = vals
         want = S.A[p].toarray()[0]
         assert np.abs(row - want).max() <= 1e-13 * np.abs(want).max()
+
+
+# ------------------------------------------------------ subgroup arrays --
+from oracle.p2 import SUBGROUPS, subgroup_arrays, subgroup_width  # noqa: E402
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_subgroup_widths_follow_the_table(level):
+    """Vertex width 2^l + 1, six edge subgroups 2^l, xyz 2^l - 1 (subgroup
+    table); the shifted index polytopes cover the next level's vertices
+    exactly once."""
+    n = 2 ** level
+    assert [subgroup_width(g, level) for g in range(8)] == [n + 1] + [n] * 6 + [n - 1]
+    from oracle.p2 import SUBGROUP_SHIFT
+    seen = set()
+    for g in range(8):
+        w = subgroup_width(g, level)
+        for k in range(w):
+            for j in range(w - k):
+                for i in range(w - k - j):
+                    p = tuple(2 * np.array((i, j, k)) + SUBGROUP_SHIFT[g])
+                    assert sum(p) <= 2 * n and p not in seen
+                    seen.add(p)
+    assert len(seen) == N_tet(2 * n + 1)
+
+
+def test_vertex_subgroup_is_the_tw_order_and_aos_soa_agree():
+    """On the reference tet with the identity 'function' (each node's
+    level-(l+1) local index), the vertex subgroup lists (2i, 2j, 2k) in t_w
+    order (the paper's z-down example order for level 2 reappears at the
+    vertices), and AoS / SoA hold the same structures (eq. for AoS and SoA)."""
+    xyz, cells = mesh_by_name("ref_tet")
+    level, m = 2, 3
+    n2 = 2 ** (level + 1)
+
+    def vals(keys):
+        w = np.zeros((len(keys), 4), dtype=np.int64)
+        ids, wt = keys[:, 0::2], keys[:, 1::2]
+        for q in range(4):
+            w[:, q] = np.where(ids == cells[0][q], wt, 0).sum(axis=1)
+        return np.stack([w[:, 1], w[:, 2], w[:, 3]], axis=1).astype(float)
+
+    aos = subgroup_arrays(cells, level, vals, m, "aos")
+    soa = subgroup_arrays(cells, level, vals, m, "soa")
+    assert len(aos) == len(soa) == m * N_tet(n2 + 1)
+    nv = N_tet(2 ** level + 1)
+    v = aos[:m * nv].reshape(nv, m)
+    order = [(i, j, k) for k in range(5) for j in range(5 - k) for i in range(5 - k - j)]
+    assert np.array_equal(v, 2 * np.array(order, dtype=float))
+    off = 0
+    for g in range(8):
+        w = subgroup_width(g, level)
+        N = N_tet(w)
+        a = aos[off:off + m * N].reshape(N, m)
+        s = soa[off:off + m * N].reshape(m, N)
+        assert np.array_equal(a, s.T), SUBGROUPS[g]
+        off += m * N
