@@ -461,8 +461,12 @@ static void check_stored_level(int level, int dtype) {
 }
 
 // ------------------------------------------------------------- P2 --------
-// Rows per bulk tile of the P2 kernel (the five planes of J + 4 rows and the
-// J x 2 x 3 shift sums stay in registers).
+// Bulk P2 kernel: k-march segments of p2_march_rows() rows (five planes of
+// J + 4 rows in a register ring), or plane tiles of kP2J rows.
+// (measured at P2 level 7: J = 2 in FP64, J = 4 in FP32, 40-plane segments)
+static const bool kP2March = true;
+static int p2_march_rows(int dtype) { return dtype == HT_F64 ? 2 : 4; }
+static const int kP2MarchSeg = 40;  // planes per march segment, multiple of 10
 static const int kP2J = 4;
 
 // Level-scaled P2 stencils of every cell, K / 2^l at P2 level l.
@@ -502,6 +506,18 @@ static std::vector<int2> make_p2_tiles(int n, int J) {
         t.push_back(make_int2(k | (j0 << 16), i0));
   return t;
 }
+// k-march segments of one cell at fine n: (j0 | k0 << 16, i0) for rows
+// j0 .. j0 + J - 1, points i0 + 2 .. i0 + 125 and planes k0 .. k0 + seg - 1
+// up to the last plane where row j0 has a point 1 <= i <= e - 1.
+static std::vector<int2> make_p2_columns(int n, int J, int seg) {
+  std::vector<int2> t;
+  for (int j0 = 0; n - j0 >= 2; j0 += J)
+    for (int i0 = -2; i0 + 2 <= n - j0 - 1; i0 += kP2TileI) {
+      const int kcol = n - j0 - std::max(2, i0 + 3);
+      for (int k0 = 0; k0 <= kcol; k0 += seg) t.push_back(make_int2(j0 | (k0 << 16), i0));
+    }
+  return t;
+}
 // Face runs of one cell: (k | side << 16 | s << 17, j0) for the points
 // j = j0 + 2 lane + s of plane k on face i = 0 (side 0, j + k <= n) or on
 // the slanted face (side 1, j + k <= n - 1).
@@ -525,10 +541,12 @@ static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   Mesh& m = h->m;
   const int lf = level + 1;
   const CellLayout L = make_layout(lf);
-  auto tiles = h->p2_tiles.find({lf, kP2J});
+  const int J = kP2March ? p2_march_rows(dtype) : kP2J;
+  const int key = kP2March ? -J : J;  // columns and plane tiles cached apart
+  auto tiles = h->p2_tiles.find({lf, key});
   if (tiles == h->p2_tiles.end()) {
-    auto t = make_p2_tiles(L.n, kP2J);
-    tiles = h->p2_tiles.emplace(std::make_pair(lf, kP2J),
+    auto t = kP2March ? make_p2_columns(L.n, J, kP2MarchSeg) : make_p2_tiles(L.n, J);
+    tiles = h->p2_tiles.emplace(std::make_pair(lf, key),
                                 std::make_pair(upload(t), (int64_t)t.size())).first;
   }
   auto runs = h->p2_runs.find(lf);
@@ -548,18 +566,20 @@ static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   a.nc = m.nc;
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
   a.n = L.n;
+  a.march = kP2March ? 1 : 0;
+  a.kseg = kP2MarchSeg;
   {
     P2Args b = a;  // bulk kernel only
     b.nfblk = 0;
     Prof p(h, "cell_p2", s);
-    launch_p2(dtype, kP2J, b, s);
+    launch_p2(dtype, J, b, s);
     check_launch();
   }
   {
     P2Args f = a;  // face kernel only
     f.nblk = 0;
     Prof p(h, "face_p2", s);
-    launch_p2(dtype, kP2J, f, s);
+    launch_p2(dtype, J, f, s);
     check_launch();
   }
   ExchArgs ea = exch_args(h, lf, y, nullptr, nullptr, 0.0, m.d_partials, full_range(m));

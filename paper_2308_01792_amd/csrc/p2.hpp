@@ -128,6 +128,8 @@ struct P2Args {
   int64_t nc;
   int64_t stride, off_s0, off_s1;
   int n;                  // fine intervals per macro-edge, 2^(l+1)
+  int march;              // bulk tiles are k-march segments (j0 | k0 << 16, i0)
+  int kseg;               // planes per k-march segment (a multiple of 10)
 };
 enum { kP2TileI = 124 };
 
