@@ -49,7 +49,7 @@ struct ht_mesh {
   // (level, dtype) -> (J, waves side by side in i) of the sweep operations
   std::map<std::pair<int, int>, std::pair<int, bool>> tuned_sweep;
   std::map<int, double> lambda_max;            // level -> estimate
-  // (fine level, J) -> P2 bulk tiles; fine level -> P2 face runs
+  // (fine level, J) -> P2 k-march segments; fine level -> P2 face runs
   std::map<std::pair<int, int>, std::pair<int2*, int64_t>> p2_tiles;
   std::map<int, std::pair<int2*, int64_t>> p2_runs;
   // P2 level -> subgroup rows (g, k, j, element offset) of one cell
@@ -462,12 +462,10 @@ static void check_stored_level(int level, int dtype) {
 
 // ------------------------------------------------------------- P2 --------
 // Bulk P2 kernel: k-march segments of p2_march_rows() rows (five planes of
-// J + 4 rows in a register ring), or plane tiles of kP2J rows.
-// (measured at P2 level 7: J = 2 in FP64, J = 4 in FP32, 40-plane segments)
-static const bool kP2March = true;
+// J + 4 rows in a register ring); measured at P2 level 7: J = 2 in FP64,
+// J = 4 in FP32, 40-plane segments.
 static int p2_march_rows(int dtype) { return dtype == HT_F64 ? 2 : 4; }
 static const int kP2MarchSeg = 40;  // planes per march segment, multiple of 10
-static const int kP2J = 4;
 
 // Level-scaled P2 stencils of every cell, K / 2^l at P2 level l.
 static const void* p2_weights(ht_mesh* h, int level, int dtype) {
@@ -495,17 +493,6 @@ static const void* p2_weights(ht_mesh* h, int level, int dtype) {
   return dtype == HT_F64 ? (const void*)m.d_p2w64[level] : (const void*)m.d_p2w32[level];
 }
 
-// Bulk tiles of one cell at fine n: plane k, rows j0 .. j0 + J - 1, points
-// i0 + 2 .. i0 + 125 (lanes 1 .. 62 of a wave holding i0 .. i0 + 127); only
-// tiles whose first (longest) row has a point with 1 <= i <= e - 1.
-static std::vector<int2> make_p2_tiles(int n, int J) {
-  std::vector<int2> t;
-  for (int k = 0; k <= n; ++k)
-    for (int j0 = 0; n - j0 - k >= 2; j0 += J)
-      for (int i0 = -2; i0 + 2 <= n - j0 - k - 1; i0 += kP2TileI)
-        t.push_back(make_int2(k | (j0 << 16), i0));
-  return t;
-}
 // k-march segments of one cell at fine n: (j0 | k0 << 16, i0) for rows
 // j0 .. j0 + J - 1, points i0 + 2 .. i0 + 125 and planes k0 .. k0 + seg - 1
 // up to the last plane where row j0 has a point 1 <= i <= e - 1.
@@ -541,12 +528,11 @@ static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   Mesh& m = h->m;
   const int lf = level + 1;
   const CellLayout L = make_layout(lf);
-  const int J = kP2March ? p2_march_rows(dtype) : kP2J;
-  const int key = kP2March ? -J : J;  // columns and plane tiles cached apart
-  auto tiles = h->p2_tiles.find({lf, key});
+  const int J = p2_march_rows(dtype);
+  auto tiles = h->p2_tiles.find({lf, J});
   if (tiles == h->p2_tiles.end()) {
-    auto t = kP2March ? make_p2_columns(L.n, J, kP2MarchSeg) : make_p2_tiles(L.n, J);
-    tiles = h->p2_tiles.emplace(std::make_pair(lf, key),
+    auto t = make_p2_columns(L.n, J, kP2MarchSeg);
+    tiles = h->p2_tiles.emplace(std::make_pair(lf, J),
                                 std::make_pair(upload(t), (int64_t)t.size())).first;
   }
   auto runs = h->p2_runs.find(lf);
@@ -566,7 +552,6 @@ static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   a.nc = m.nc;
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
   a.n = L.n;
-  a.march = kP2March ? 1 : 0;
   a.kseg = kP2MarchSeg;
   {
     P2Args b = a;  // bulk kernel only

@@ -113,22 +113,21 @@ enum { kP2PerCell = kP2Parities * kNumClasses * kP2MaxOffsets };
 // by 2^l, the micro-cells being the unit shapes scaled by 2^-l).
 void p2_cell_weights(const double X[4][3], double* w /* [kP2PerCell] */);
 
-// Work of one cell for the bulk kernel: tiles (k | j0 << 16, i0) of J rows x
-// 124 points; for the face kernel: runs (k | side << 16 | s << 17, j0) of the
+// Work of one cell for the bulk kernel: k-march segments (j0 | k0 << 16, i0)
+// of J rows x 124 points from plane k0; for the face kernel: runs (k | side << 16 | s << 17, j0) of the
 // 64 points j = j0 + 2 lane + s of face i = 0 (side 0) or i = n - j - k
 // (side 1) in plane k.
 struct P2Args {
   const void* x;
   void* y;
   const void* w;          // [nc][kP2PerCell] level-scaled weights
-  const int2* tiles;      // bulk tiles of one cell
+  const int2* tiles;      // k-march segments of one cell
   int64_t ntiles, nblk;   // tiles per cell, blocks per cell
   const int2* runs;       // face runs of one cell
   int64_t nruns, nfblk;
   int64_t nc;
   int64_t stride, off_s0, off_s1;
   int n;                  // fine intervals per macro-edge, 2^(l+1)
-  int march;              // bulk tiles are k-march segments (j0 | k0 << 16, i0)
   int kseg;               // planes per k-march segment (a multiple of 10)
 };
 enum { kP2TileI = 124 };
