@@ -137,11 +137,23 @@ static const int kDefaultJ = 4;
 
 // Tile groups of the stencil kernel: 62 output i x (kCellWaves x J rows),
 // or (62 kCellWaves) i x J rows when the waves sit side by side in i.
-static std::vector<int2> make_tiles(int n, int J, bool in_i) {
+// Planes per march segment of the stencil kernel's tiles: splitting a column
+// into segments (each reloads two planes) evens out the work per wave;
+// measured at level 8, 64 suits the stacked arrangement, 32 the side-by-side
+// one.
+static int march_segment(bool in_i) { return in_i ? 32 : 64; }
+
+// Tiles (i0, j0) of one cell; with `segmented` (the stencil kernel) each tile
+// is split into march segments (i0, j0 | k0 << 16).
+static std::vector<int2> make_tiles(int n, int J, bool in_i, bool segmented = false) {
   std::vector<int2> t;
   const int GJ = in_i ? J : kCellWaves * J, GI = in_i ? 62 * kCellWaves : 62;
+  const int seg = march_segment(in_i);
   for (int tj = 0; GJ * tj <= n; ++tj)
-    for (int ti = 0; GI * ti + GJ * tj <= n; ++ti) t.push_back(make_int2(GI * ti, GJ * tj));
+    for (int ti = 0; GI * ti + GJ * tj <= n; ++ti) {
+      const int kcol = segmented ? n - GI * ti - GJ * tj : 0;
+      for (int k0 = 0; k0 <= kcol; k0 += seg) t.push_back(make_int2(GI * ti, GJ * tj | (k0 << 16)));
+    }
   return t;
 }
 
@@ -158,7 +170,7 @@ static int64_t partials_needed(const ht_mesh* h, int level) {
   int64_t cell_blocks = 0;
   for (int J : kJ)
     for (bool in_i : {false, true})
-      cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J, in_i).size());
+      cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J, in_i, true).size());
   const int64_t fp = n_tri(n - 2), total = m.n_faces * fp + m.n_edges * std::max(n - 1, 0) + m.n_verts;
   const int64_t exch_blocks = (total + 255) / 256;
   const int64_t elem_blocks = m.nc * (int64_t)make_walk_tiles(n).size();
@@ -223,7 +235,7 @@ void ensure_uploaded_h(ht_mesh* h) {
     m.d_w32[l] = upload(wf);
     for (int J : kJ)
       for (bool in_i : {false, true}) {
-        auto t = make_tiles(1 << l, J, in_i);
+        auto t = make_tiles(1 << l, J, in_i, true);
         h->tiles[{l, J, in_i}] = {upload(t), (int64_t)t.size()};
       }
     {
@@ -310,6 +322,7 @@ static CellArgs cell_args(ht_mesh* h, int level, int dtype, const Shape& sh,
   a.partials = m.d_partials;
   auto& t = h->tiles.at({level, sh.J, sh.in_i});
   a.waves_in_i = sh.in_i ? 1 : 0;
+  a.kseg = march_segment(sh.in_i);
   a.tiles = t.first;
   a.ntiles = t.second;
   a.nblocks = (R.c1 - R.c0) * t.second;
@@ -413,11 +426,13 @@ static const void* vcoef_couplings(ht_mesh* h, int level, int dtype) {
   return dtype == HT_F64 ? (const void*)m.d_kc64[level] : (const void*)m.d_kc32[level];
 }
 
+// Unsegmented tiles for the variable-coefficient kernel, cached under -J so
+// that they never mix with the stencil kernel's segmented tiles.
 static const std::pair<int2*, int64_t>& tiles_of(ht_mesh* h, int level, int J) {
-  auto it = h->tiles.find({level, J, false});
+  auto it = h->tiles.find({level, -J, false});
   if (it == h->tiles.end()) {
     auto t = make_tiles(1 << level, J, false);
-    it = h->tiles.emplace(std::make_tuple(level, J, false),
+    it = h->tiles.emplace(std::make_tuple(level, -J, false),
                           std::make_pair(upload(t), (int64_t)t.size())).first;
   }
   return it->second;

@@ -67,7 +67,10 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   const int64_t wb = (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
   if (wb >= nb) return;
   const int64_t cell = wb / a.ntiles;
-  const int2 tile = a.tiles[wb % a.ntiles];
+  // tile (i0, j0 | k0 << 16): the march covers planes k0 .. k0 + segment - 1
+  const int2 tile_raw = a.tiles[wb % a.ntiles];
+  const int k0 = tile_raw.y >> 16;
+  const int2 tile = make_int2(tile_raw.x, tile_raw.y & 0xffff);
   const int lane = threadIdx.x & 63;
   // wave index, uniform over the wave: say so, so that the row bookkeeping
   // derived from it lives in scalar registers
@@ -125,7 +128,10 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   // Each plane advances them by its own size, so no plane recomputes the
   // tetrahedral numbers.
   const int wm = n - 1;  // width of the main block's polytope
-  int ck = 0, cmb = -1, csa = off_s0, csb = off_s1;
+  // (started at plane k0 - 1, or 0, from the closed forms of the plane sizes)
+  int ck = k0 > 0 ? k0 - 1 : 0;
+  int cmb = -1 + tet32(wm) - tet32(wm - ck), csa = off_s0 + tri32(n + 1) - tri32(n + 1 - ck),
+      csb = off_s1 + tri32(n) - tri32(n - ck);
   auto advance = [&]() {
     const int wk = wm - ck;
     cmb += wk > 0 ? wk * (wk + 1) / 2 : 0;
@@ -325,12 +331,21 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
   T PA[J + 2], PB[J + 2], PC[J + 2], PD[J + 2];
   unsigned OA[J + 2], OB[J + 2], OC[J + 2], OD[J + 2];
   T BA[J], BB[J], DA[J], DB[J];
+  if (k0 > 0) {
+    plane_offsets(OA);
+#pragma unroll
+    for (int r = 0; r < J + 2; ++r) bload(PA[r], rx, OA[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < J + 2; ++r) {
+      PA[r] = (T)0;
+      OA[r] = HT_OOB;
+    }
+  }
   plane_offsets(OB);
   plane_offsets(OC);
 #pragma unroll
   for (int r = 0; r < J + 2; ++r) {
-    PA[r] = (T)0;
-    OA[r] = HT_OOB;
     bload(PB[r], rx, OB[r]);
     bload(PC[r], rx, OC[r]);
   }
@@ -346,9 +361,11 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
       for (int r = 0; r < J; ++r) bload(DA[r], rd, OB[r + 1]);
     }
   }
-  mask_plane(0, PB);
-  const int kmax = n - i0 - j0;
-  for (int k = 0; k <= kmax; k += 4) {
+  if (k0 > 0) mask_plane(k0 - 1, PA);
+  mask_plane(k0, PB);
+  const int kcol = n - i0 - j0;
+  const int kmax = kcol < k0 + a.kseg - 1 ? kcol : k0 + a.kseg - 1;
+  for (int k = k0; k <= kmax; k += 4) {
     step(k, PA, PB, PC, PD, OB, OC, OD, BA, BB, DA, DB);
     if (k + 1 > kmax) break;
     step(k + 1, PB, PC, PD, PA, OC, OD, OA, BB, BA, DB, DA);

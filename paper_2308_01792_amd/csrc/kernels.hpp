@@ -49,6 +49,7 @@ struct CellArgs {
   // wave arrangement of a workgroup: 0 = stacked in j (rows j0 .. j0 +
   // kCellWaves J - 1), 1 = side by side in i (62 kCellWaves points of J rows)
   int waves_in_i;
+  int kseg;             // planes per march segment of a tile (tiles carry k0)
   double omega, nscale; // nscale = 2^l (inverse diagonal scale)
   // restriction output (coarse level layout)
   int64_t stride_out, off_s0_out, off_s1_out;
