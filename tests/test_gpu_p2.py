@@ -256,3 +256,49 @@ def test_p2_subgroup_arrays_match_oracle(name, level, m, dtype, layout):
     real = torch.as_tensor(np.tile(p.idx >= 0, m), device="cuda")
     assert torch.equal(back[real], lat[real])
     p.m.close()
+
+
+# ------------------------------------------------------------ max level --
+def test_p2_sampled_rows_at_the_largest_level():
+    """P2 level 9 (the level-10 lattice, the largest the library accepts):
+    three jittered cells sharing faces and an edge, rows at points spread
+    over the cell blocks and their far ends against the single-row oracle."""
+    from workloads import slab
+    level = 9
+    fine = level + 1
+    n = 2 ** fine
+    xyz, cells = slab(1, 3, amplitude=0.1, seed=7)
+    m = ht.Mesh(xyz, cells, fine, fine)
+    g = torch.Generator(device="cuda").manual_seed(12)
+    x = torch.rand(m.n_slots(fine), dtype=torch.float64, device="cuda",
+                   generator=g) * 2 - 1
+    m.sync(fine, x)
+    y = torch.full_like(x, float("nan"))
+    m.apply_p2(level, x, y)
+    torch.cuda.synchronize()
+    pts = []
+    for c in range(3):
+        pts += [(c, 1, 1, 1), (c, 2, 1, 1), (c, 1, 2, 1), (c, 1, 1, 2),
+                (c, n // 2, n // 3, n // 7), (c, 1, 1, n - 3), (c, n - 3, 1, 1),
+                (c, 1, n - 3, 1), (c, 125, 126, n - 252), (c, 0, 5, n - 9),
+                (c, 5, 0, n - 9), (c, n - 14, 5, 9), (c, 0, 0, n // 2),
+                (c, 3, n - 5, 1), (c, n - 4, 2, 1)]
+    checked = 0
+    for (c, i, j, k) in pts:
+        slot = m.slot_index(fine, c, i, j, k)
+        key, _ = m.keys(fine, slot, 1)
+        nbr, vals, dirichlet = p2_row_at(xyz, cells, level, key[0])
+        got = float(y[slot])
+        if dirichlet:
+            assert got == 0.0
+            continue
+        ns = np.array([_slot_of_key(m, cells, fine, kk) for kk in nbr])
+        xv = x[torch.as_tensor(ns, device="cuda")].cpu().numpy()
+        want = float(vals @ xv)
+        assert abs(got - want) <= 1e-12 * float(np.abs(vals) @ np.abs(xv)), \
+            ((c, i, j, k), got, want)
+        checked += 1
+    assert checked >= 20
+    del x, y
+    m.close()
+    torch.cuda.empty_cache()
