@@ -30,8 +30,6 @@
 namespace ht {
 namespace {
 
-__constant__ P2Offsets kP2OffDev = make_p2_offsets();
-
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
   (f(std::integral_constant<int, I>{}), ...);
