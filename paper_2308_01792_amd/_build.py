@@ -18,8 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhytet.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mesh.cpp", "abi.cpp", "kernels.hip", "walk.hip", "vcoef.hip",
-           "p2.hip", "p2_host.cpp"]
+SOURCES = ["mesh.cpp", "abi.cpp", "kernels.hip", "band.hip", "walk.hip",
+           "vcoef.hip", "p2.hip", "p2_host.cpp"]
 ARCH = os.environ.get("HYTET_ARCH", "gfx950")
 
 

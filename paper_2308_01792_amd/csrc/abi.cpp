@@ -2,6 +2,7 @@
 // sequencing of operators, V-cycles, iterative refinement and graphs.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include "hytet_impl.hpp"
 #include "p2.hpp"
 #include "kernels.hpp"
+#include "band.hpp"
 #include "vcoef.hpp"
 
 struct ht_mesh;
@@ -46,6 +48,9 @@ struct ht_mesh {
   // level -> walk tiles (64 i x 8 rows) for the transfer / elementwise kernels
   std::map<int, std::pair<int2*, int64_t>> walk_tiles;
   std::map<std::pair<int, int>, int> tuned_J;  // (level, dtype) -> J
+  // (level, dtype) -> band-kernel work items of one cell (absent where no
+  // band fits the LDS image capacity)
+  std::map<std::pair<int, int>, std::pair<int2*, int64_t>> band_items;
   // (level, dtype) -> (J, waves side by side in i) of the sweep operations
   std::map<std::pair<int, int>, std::pair<int, bool>> tuned_sweep;
   std::map<int, double> lambda_max;            // level -> estimate
@@ -242,6 +247,11 @@ void ensure_uploaded_h(ht_mesh* h) {
       auto t = make_walk_tiles(1 << l);
       h->walk_tiles[l] = {upload(t), (int64_t)t.size()};
     }
+    for (int dt : {HT_F64, HT_F32}) {
+      std::vector<int2> it;
+      if (make_band_items(1 << l, band_cap(dt == HT_F64), kBandMinRows, it))
+        h->band_items[{l, dt}] = {upload(it), (int64_t)it.size()};
+    }
     pcap = std::max(pcap, partials_needed(h, l));
   }
   m.d_partials = dalloc<double>(pcap);
@@ -281,10 +291,27 @@ static void check_launch() {
 }
 
 // -------------------------------------------------------- operators -----
+// Tile rows of the apply; 0 selects the band kernel (band.hip), the FP64
+// default wherever its LDS image fits (measured faster than every tile
+// shape in FP64 at level 8, slower in FP32, where tile rows 4 stay the
+// default).  The autotuner times both.
+static bool has_band(const ht_mesh* h, int level, int dtype) {
+  (void)h;
+  // a function of (level, dtype) only: tabulated once
+  static const std::vector<std::array<bool, 2>> ok = [] {
+    std::vector<std::array<bool, 2>> t(kBandMaxLevel + 1);
+    std::vector<int2> it;
+    for (int l = 0; l <= kBandMaxLevel; ++l)
+      for (int d = 0; d < 2; ++d)
+        t[l][d] = make_band_items(1 << l, band_cap(d == HT_F64), kBandMinRows, it);
+    return t;
+  }();
+  return level >= 0 && level <= kBandMaxLevel && ok[level][dtype == HT_F64 ? 0 : 1];
+}
 static int choose_J(ht_mesh* h, int level, int dtype) {
   auto it = h->tuned_J.find({level, dtype});
   if (it != h->tuned_J.end()) return it->second;
-  return kDefaultJ;
+  return dtype == HT_F64 && has_band(h, level, dtype) ? 0 : kDefaultJ;
 }
 
 // Tile shape of a stencil launch: rows per wave and wave arrangement.  The
@@ -297,7 +324,11 @@ struct Shape {
   bool in_i;
 };
 static Shape choose_shape(ht_mesh* h, int level, int dtype, int op) {
-  if (!op_is_sweep(op)) return Shape{choose_J(h, level, dtype), false};
+  if (op == OP_APPLY) return Shape{choose_J(h, level, dtype), false};
+  if (!op_is_sweep(op)) {
+    const int J = choose_J(h, level, dtype);
+    return Shape{J == 0 ? kDefaultJ : J, false};
+  }
   auto it = h->tuned_sweep.find({level, dtype});
   if (it != h->tuned_sweep.end()) return Shape{it->second.first, it->second.second};
   return Shape{kDefaultJ, (1 << level) >= 62 * (kCellWaves - 1) + 1};
@@ -330,6 +361,23 @@ static CellArgs cell_args(ht_mesh* h, int level, int dtype, const Shape& sh,
   a.n = L.n;
   a.omega = omega;
   a.nscale = (double)L.n;
+  return a;
+}
+
+// Band-kernel arguments over the cells of R.
+static BandArgs band_args(ht_mesh* h, int level, int dtype, const void* x, void* y,
+                          const Range& R) {
+  const CellLayout L = make_layout(level);
+  BandArgs a{};
+  a.x = at_cell(x, R.c0, level, dtype);
+  a.y = at_cell(y, R.c0, level, dtype);
+  a.w = (const char*)level_weights(h, level, dtype) + R.c0 * 240 * (int64_t)esize(dtype);
+  const auto& it = h->band_items.at({level, dtype});
+  a.items = it.first;
+  a.nitems = it.second;
+  a.nblocks = (R.c1 - R.c0) * it.second;
+  a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
+  a.n = L.n;
   return a;
 }
 
@@ -371,6 +419,20 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
   Mesh& m = h->m;
   if (R.empty()) return;
   const Shape sh = choose_shape(h, level, dtype, op);
+  if (op == OP_APPLY && sh.J == 0) {
+    {
+      Prof p(h, "cell_apply", s);
+      launch_band(dtype, op, band_args(h, level, dtype, x, y, R), s);
+      check_launch();
+    }
+    ExchArgs ea = exch_args(h, level, y, nullptr, nullptr, omega, m.d_partials, R);
+    if (ea.total > 0) {
+      Prof p(h, "exchange", s);
+      launch_exchange(dtype, op, ea, s);
+      check_launch();
+    }
+    return;
+  }
   CellArgs ca = cell_args(h, level, dtype, sh, x, y, b, omega, R);
   ca.y32 = at_cell(y32, R.c0, level, HT_F32);
   {
@@ -1135,6 +1197,7 @@ int ht_mesh_destroy(ht_mesh* h) {
       for (auto& kv : m.graphs) (void)hipGraphExecDestroy(kv.second.exec);
       for (auto& kv : h->tiles) (void)hipFree(kv.second.first);
       for (auto& kv : h->walk_tiles) (void)hipFree(kv.second.first);
+      for (auto& kv : h->band_items) (void)hipFree(kv.second.first);
       for (auto* p : m.d_w64) if (p) (void)hipFree(p);
       for (auto* p : m.d_w32) if (p) (void)hipFree(p);
       for (auto* p : m.d_kc64) if (p) (void)hipFree(p);
@@ -1957,8 +2020,9 @@ int ht_set_tile_rows(ht_mesh* h, int level, int dtype, int rows) {
     if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
     check_level(h->m, level);
     check_dtype(dtype);
-    if (rows != 4 && rows != 8 && rows != 16)
-      throw Error{HT_ERR_ARG, "tile rows must be 4, 8 or 16"};
+    if (rows != 4 && rows != 8 && rows != 16 && !(rows == 0 && has_band(h, level, dtype)))
+      throw Error{HT_ERR_ARG, "tile rows must be 4, 8 or 16, or 0 (band kernel) where "
+                              "its LDS image fits the level"};
     h->tuned_J[{level, dtype}] = rows;
   });
 }
@@ -1968,8 +2032,7 @@ int ht_get_tile_rows(const ht_mesh* h, int level, int dtype, int* rows) {
     if (!h || !rows) throw Error{HT_ERR_ARG, "NULL argument"};
     check_level(h->m, level);
     check_dtype(dtype);
-    auto it = h->tuned_J.find({level, dtype});
-    *rows = it == h->tuned_J.end() ? kDefaultJ : it->second;
+    *rows = choose_J(const_cast<ht_mesh*>(h), level, dtype);
   });
 }
 
@@ -2011,6 +2074,7 @@ int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
     key << prop.gcnArchName << ' ' << level << ' ' << dtype << ' ' << h->m.nc
         << ' ' << L.stride << " v2";
     auto valid_rows = [](int J) { return J == 4 || J == 8 || J == 16; };
+    auto valid_apply = [&](int J) { return valid_rows(J) || (J == 0 && has_band(h, level, dtype)); };
     if (cache_path) {
       FILE* f = std::fopen(cache_path, "r");
       if (f) {
@@ -2020,7 +2084,7 @@ int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
           int J = 0, sJ = 0, sI = -1;
           if (ln.compare(0, k.size(), k) == 0 &&
               std::sscanf(ln.c_str() + k.size(), "%d %d %d", &J, &sJ, &sI) == 3 &&
-              valid_rows(J) && valid_rows(sJ) && (sI == 0 || sI == 1)) {
+              valid_apply(J) && valid_rows(sJ) && (sI == 0 || sI == 1)) {
             h->tuned_J[{level, dtype}] = J;
             h->tuned_sweep[{level, dtype}] = {sJ, sI == 1};
             if (rows) *rows = J;
@@ -2057,12 +2121,15 @@ int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
       HT_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
       return ms;
     };
-    int best = kDefaultJ;
+    int best = choose_J(h, level, dtype);
     std::pair<int, bool> best_sweep{kDefaultJ, true};
     try {
-      // apply: rows per wave, waves stacked in j
+      // apply: the band kernel, or the tile kernel with J rows per wave and
+      // the waves stacked in j
       float best_ms = 1e30f;
-      for (int J : kJ) {
+      std::vector<int> cand(std::begin(kJ), std::end(kJ));
+      if (has_band(h, level, dtype)) cand.insert(cand.begin(), 0);
+      for (int J : cand) {
         h->tuned_J[{level, dtype}] = J;
         const float ms = time_of([&] { op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s); });
         if (ms < best_ms) { best_ms = ms; best = J; }

@@ -324,12 +324,15 @@ def test_solve_mixed_precision():
     assert err <= 1e-8
 
 
-@pytest.mark.parametrize("rows", [4, 8, 16])
+@pytest.mark.parametrize("rows", [0, 4, 8, 16])
 @pytest.mark.parametrize("name,level", [("jittered_288", 4), ("ref_tet", 6),
-                                        ("slab_3_11", 5)])
+                                        ("slab_3_11", 5), ("ref_tet", 7)])
 def test_apply_every_tile_shape(name, level, rows):
-    """All stencil-kernel tile shapes (64 i x rows) give the oracle's result,
-    for both precisions and for residual and Jacobi epilogues."""
+    """All stencil-kernel tile shapes (64 i x rows, and 0: the band kernel
+    with whole rows staged in LDS) give the oracle's result, for both
+    precisions and, for the tile shapes, the residual and Jacobi epilogues.
+    The reference tet at level 7 gives the band kernel several bands and
+    plane segments per cell."""
     P = pair(name, level, level)
     S = P.S(level)
     N = S.mesh.num_vertices
@@ -343,6 +346,9 @@ def test_apply_every_tile_shape(name, level, rows):
         yg = torch.zeros_like(xg)
         P.m.apply(level, xg, yg)
         assert rel_err(P.from_gpu(level, yg), S.apply(x)) <= tol
+        if rows == 0:
+            P.m.set_tile_rows(level, code, 8)
+            continue
         for in_i in (False, True):      # both workgroup arrangements
             P.m.set_sweep_shape(level, code, rows, in_i)
             assert P.m.sweep_shape(level, code) == (rows, in_i)
@@ -360,7 +366,7 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     P = pair("jittered_288", 4, 4)
     cache = str(tmp_path / "tune.txt")
     rows = P.m.autotune(4, ht.HT_F64, cache)
-    assert rows in (4, 8, 16) and P.m.tile_rows(4, ht.HT_F64) == rows
+    assert rows in (0, 4, 8, 16) and P.m.tile_rows(4, ht.HT_F64) == rows
     sweep = P.m.sweep_shape(4, ht.HT_F64)
     assert sweep[0] in (4, 8, 16)
     P.m.set_tile_rows(4, ht.HT_F64, 4 if rows != 4 else 8)
