@@ -8,9 +8,9 @@
 // workgroup owns a band of whole rows of one cell, and
 //   * loads each plane of the band once, as one contiguous run of the main
 //     block plus the band's face entries, into an LDS image (band.hpp);
-//   * assigns lanes to consecutive image positions, so a wave's 62 outputs
-//     are consecutive closure points, possibly spanning several rows, and
-//     its stores form one contiguous run of the main block;
+//   * assigns each lane two consecutive image positions, so a wave's 124
+//     outputs are consecutive closure points, possibly spanning several
+//     rows, and its stores form one contiguous run of the main block;
 //   * keeps a four-plane ring in LDS (planes k - 1, k, k + 1 are read while
 //     plane k + 2 is written) and four more planes in flight from HBM.
 // The workgroup's waves are split by role: four load waves stream the band's
@@ -28,6 +28,8 @@
 // for the ghost exchange (Section 5.2, element-wise assembly restricted to
 // the micro-cells of one macro-cell).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "band.hpp"
 #include "device.hpp"
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandArgs a) {
 
   if (wave >= kBandComputeWaves) {
     // ---------------------------------------------------- load waves --
-    // Plane q of the band: load lane t holds image positions t + 256 m.
+    // Plane q of the band: load lane t holds image positions t + m kBandLoadLanes.
     // Row r of the image is closure row jm + r: its first point (i = 0) is
     // in S0, its last (i = e) in S1, the others in the main block, where
     // consecutive rows follow each other (the main-block element of image
@@ -214,11 +216,17 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandArgs a) {
     // column, whose pair is not output), so the i +- 1 terms need one lane
     // shift per point pair instead of two per point, and each row's two
     // values come from one paired LDS read.
-    const int nch = (Ue - Ub + 123) / 124;
-    // the band's first output row holds j = 0 (face j = 0)
-    const bool row0 = j0 == 0;
-    for (int ch = wave; ch < nch; ch += kBandComputeWaves) {
-      const int P = Ub + 124 * ch - 2;
+    // The pair grid starts at G = Ub or Ub - 1 so that A always maps to an
+    // even main-block element: a pair inside a row is then one aligned
+    // two-value store, and a wave's stores cover whole cache lines.
+    const int G = Ub - ((Kc + Ub) & 1);
+    const int nch = (Ue - G + 123) / 124;
+    // One chunk: the 124 outputs of lanes 1 .. 62.  SPECIAL chunks may hold
+    // points of the faces j = 0 (row 1 of the band j0 = 0) or k = 0 and take
+    // per-lane class stencils; the others take the cell's interior stencil.
+    auto chunk = [&](int ch, auto special) {
+      constexpr bool SPECIAL = decltype(special)::value;
+      const int P = G + 124 * ch - 2;
       const int Ar = P + 2 * lane;
       const int A = Ar < Ub ? Ub : (Ar > Ue - 1 ? Ue - 1 : Ar);
       int Dr;
@@ -236,7 +244,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandArgs a) {
       const T xkmA = ring[e5], xkmB = ring[e5 + 1];        // ( 0, -1)
       const T xjpkmA = ring[e6], xjpkmB = ring[e6 + 1];    // (+1, -1)
       T accA, accB;
-      if (k != 0 && !(row0 && P < Ub + L0 + 1)) {
+      if (!SPECIAL) {
         // Interior weights are the same on every lane, and a lane shift is
         // linear: the i + 1 terms of B (offsets 1, 8, 10, 13) are formed at
         // A's column of the next lane and the i - 1 terms of A (offsets 2,
@@ -255,7 +263,6 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandArgs a) {
         accA += lane_prev(tB);
         accB += lane_next(tA);
       } else {
-        // faces j = 0 (row j0 = 0) and k = 0: per-lane class stencil
         const int cls = ((jm + r == 0) << 1) | ((k == 0) << 2);
         const T* W = wtab + cls * 15;
         T a = W[0] * xcA, b = W[0] * xcB;
@@ -282,9 +289,25 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandArgs a) {
       const bool stA = out && c >= 2 && c <= Lr - 1;
       const bool stB = out && A + 1 <= Ue - 1 && c + 1 >= 2 && c + 1 <= Lr - 1;
       const unsigned el = (unsigned)(Kc + A - 4 * r) * (unsigned)sizeof(T);
-      bstore(accA, ry, stA ? el : HT_OOB);
-      bstore(accB, ry, stB ? el + (unsigned)sizeof(T) : HT_OOB);
+      // no branches: the chunk stays one basic block, which lets the
+      // scheduler overlap two chunks
+      bstore2(accA, accB, ry, stA && stB ? el : HT_OOB);
+      bstore(accA, ry, stA && !stB ? el : HT_OOB);
+      bstore(accB, ry, stB && !stA ? el + (unsigned)sizeof(T) : HT_OOB);
+    };
+    // chunks before nspec may touch row 1 of the band j0 = 0 (positions
+    // below D(2) = Ub + L0 + 1); on the plane k = 0 every chunk is special
+    const int nspec = k == 0 ? nch
+                      : (j0 == 0 ? min(nch, (Ub + L0 + 3 - G + 123) / 124) : 0);
+    int ch = wave;
+    for (; ch < nspec; ch += kBandComputeWaves) chunk(ch, std::true_type{});
+    // two independent chunks per iteration, so that the LDS reads of one
+    // overlap the arithmetic of the other
+    for (; ch + kBandComputeWaves < nch; ch += 2 * kBandComputeWaves) {
+      chunk(ch, std::false_type{});
+      chunk(ch + kBandComputeWaves, std::false_type{});
     }
+    if (ch < nch) chunk(ch, std::false_type{});
     // Row ends (faces i = 0 and i + j + k = n) of the output rows: lane q < R
     // takes the first point of row q + 1, lane R + q its last point.
     if (wave == (k & (kBandComputeWaves - 1))) {

@@ -23,8 +23,12 @@ namespace ht {
 // LDS image capacity (values per plane slot) and ring depth.
 // A workgroup is kBandComputeWaves compute waves and as many load waves;
 // each load lane keeps kBandDepth planes in flight.
-enum { kBandComputeWaves = 4, kBandLoadLanes = 256, kBandThreads = 512,
-       kBandSlots = 4, kBandDepth = 4, kBandRowsMax = 32 };
+#ifndef HT_BAND_WAVES
+#define HT_BAND_WAVES 4
+#endif
+enum { kBandComputeWaves = HT_BAND_WAVES, kBandLoadLanes = 64 * HT_BAND_WAVES,
+       kBandThreads = 128 * HT_BAND_WAVES, kBandSlots = 4, kBandDepth = 4,
+       kBandRowsMax = 32 };
 // Values per slot (a multiple of kBandLoadLanes): four FP64 slots are 64 KB
 // and leave room for two workgroups per CU.
 #ifndef HT_BAND_CAP64

@@ -112,6 +112,20 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r,
                                        unsigned off) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
+// Two consecutive values in one store (16 B in FP64, 8 B in FP32); the
+// offset must be a multiple of the pair's size.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc_t r,
+                                        unsigned off) {
+  const u32x2 lo = __builtin_bit_cast(u32x2, a), hi = __builtin_bit_cast(u32x2, b);
+  const u32x4 v = {lo.x, lo.y, hi.x, hi.y};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore2(float a, float b, __amdgpu_buffer_rsrc_t r,
+                                        unsigned off) {
+  const u32x2 v = {__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b)};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r,
                                        unsigned off) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
