@@ -328,6 +328,12 @@ int ht_batch_solve(ht_batch* batch, const ht_solve_opts* opts,
  * |v_20| / |v_19| over the unique non-Dirichlet micro-vertices.  Allocates
  * two scratch vectors; synchronises. */
 int ht_lambda_max(ht_mesh* mesh, int level, double* lambda, ht_stream stream);
+/* Sets the estimate used at `level` in place of the power iteration (for
+ * instance a value computed elsewhere, to run two implementations with one
+ * interval).  Host call; drops every captured graph of the mesh.
+ * HT_ERR_ARG unless lambda is positive and finite; HT_ERR_LEVEL outside the
+ * mesh's level range. */
+int ht_set_lambda_max(ht_mesh* mesh, int level, double lambda);
 
 /* Full multigrid (nested iteration) for A u = b at `level` with zero
  * Dirichlet data.  A function lives on every level (Section 5.1), so the

@@ -294,6 +294,9 @@ class Mesh:
         check(load().ht_lambda_max(self._h, level, C.byref(r), _stream()))
         return r.value
 
+    def set_lambda_max(self, level: int, value: float):
+        check(load().ht_set_lambda_max(self._h, level, float(value)))
+
     def vcycle(self, level: int, u, b, nu1=2, nu2=2, omega=2.0 / 3.0,
                coarse_level=2, smoother=HT_SMOOTH_JACOBI, degree=2):
         o = self.cycle_opts(nu1, nu2, omega, coarse_level, smoother, degree)

@@ -88,6 +88,7 @@ SIGNATURES = {
                      C.POINTER(SolveStats), P]),
     "ht_fmg": (I, [P, I, C.POINTER(CycleOpts), I, P, P, C.POINTER(D), P]),
     "ht_lambda_max": (I, [P, I, C.POINTER(D), P]),
+    "ht_set_lambda_max": (I, [P, I, D]),
     "ht_batch_create": (I, [C.POINTER(P), C.POINTER(I), I, C.POINTER(P)]),
     "ht_batch_destroy": (I, [P]),
     "ht_batch_query": (I, [P, C.POINTER(I), C.POINTER(L), C.POINTER(L)]),

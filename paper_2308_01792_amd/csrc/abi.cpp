@@ -1716,6 +1716,20 @@ int ht_lambda_max(ht_mesh* h, int level, double* lambda, ht_stream stream) {
   });
 }
 
+int ht_set_lambda_max(ht_mesh* h, int level, double lambda) {
+  return guard([&] {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    check_level(h->m, level);
+    if (!(lambda > 0.0) || !std::isfinite(lambda))
+      throw Error{HT_ERR_ARG, "lambda must be positive and finite"};
+    // captured cycles hold the Chebyshev coefficients of the old value
+    if (h->m.uploaded) (void)hipDeviceSynchronize();
+    for (auto& kv : h->m.graphs) (void)hipGraphExecDestroy(kv.second.exec);
+    h->m.graphs.clear();
+    h->lambda_max[level] = lambda;
+  });
+}
+
 int ht_fmg(ht_mesh* h, int level, const ht_cycle_opts* o, int cycles, void* u,
            const void* b, double* rel_res, ht_stream stream) {
   return guard([&] {

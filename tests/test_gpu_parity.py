@@ -202,15 +202,25 @@ def test_prolongate_add(name, coarse):
 @pytest.mark.parametrize("name,level", [("jittered_288", 2), ("kuhn_cube", 2),
                                         ("slab_3_11", 2), ("ref_tet", 3)])
 def test_coarse_solve(name, level):
+    """The library applies an inverse formed once by Cholesky; the oracle
+    solves with the Cholesky factors.  Both are backward stable, so each is
+    within a small multiple of cond(A_II) * eps of the exact solution, and
+    cond(A_II) is below 100 on these meshes (asserted): the two agree to
+    far better than 1e-12."""
     P = pair(name, level, level)
     S = P.S(level)
     N = S.mesh.num_vertices
+    I = np.flatnonzero(S.interior)
+    kappa = np.linalg.cond(S.A[I][:, I].toarray())
+    assert 16 * kappa * np.finfo(float).eps < FP64_TOL
     b = fields.uniform_values(N, 11)
     u0 = np.where(S.dirichlet, fields.uniform_values(N, 12), 0.0)
     ug = P.to_gpu(level, u0)
     P.m.coarse_solve(level, P.to_gpu(level, b), ug)
     ref = P.H.coarse_solve(level, u0, b)
-    assert rel_err(P.from_gpu(level, ug), ref) <= 1e-11
+    err = rel_err(P.from_gpu(level, ug), ref)
+    print(f"{name} level {level}: cond {kappa:.3g}, rel err {err:.2e}")
+    assert err <= FP64_TOL
 
 
 @pytest.mark.parametrize("name,level", [("jittered_288", 4), ("kuhn_cube", 5),
@@ -390,28 +400,50 @@ def test_fmg_matches_oracle(cycles):
     ug = torch.full_like(bg, np.nan)
     rel = P.m.fmg(4, ug, bg, cycles=cycles)
     uo = P.H.fmg(4, b, cycles=cycles, coarse_level=2)
-    assert rel_err(P.from_gpu(4, ug), uo) <= 1e-11
+    err = rel_err(P.from_gpu(4, ug), uo)
+    print(f"FMG with {cycles} V(2,2) per level: rel err {err:.2e}")
+    assert err <= FP64_TOL
     ro = np.linalg.norm(S.residual(uo, b)) / np.linalg.norm(b[S.interior])
     assert rel == pytest.approx(ro, rel=1e-6)
 
 
 def test_lambda_max_matches_oracle():
     """Power-iteration estimate of the largest eigenvalue of D^-1 A (the
-    Chebyshev smoother's interval): same start field, same iteration."""
+    Chebyshev smoother's interval): same start field, same iteration.
+
+    The two sides evaluate the start field sin(1000 x + 1700 y + 2300 z)
+    from their own rounding of the micro-vertex coordinates.  With
+    |x|, |y|, |z| <= 4.2 the phase is below 2e4, and a coordinate error of
+    two ulps (2e-15 at 4) moves it by up to 5000 * 2e-15 = 1e-11, plus one
+    rounding of the phase itself (ulp(2e4) = 3.6e-12): the start fields
+    differ by at most about 1.5e-11 relative.  The estimate |v_20| / |v_19|
+    is a smooth function of the start field with a derivative of order one,
+    which bounds the disagreement by about 1e-10 in the worst case.  The
+    coordinate roundings are independent and mostly below one ulp, and the
+    measured agreement is within 4e-14 on both meshes, so the test holds
+    the benchmark spec's 1e-12."""
     from oracle.mg import lambda_max_estimate
     for name, level in (("jittered_288", 4), ("slab_3_11", 3)):
-        P = pair(name, level, 2 if level > 2 else level)
-        assert P.m.lambda_max(level) == pytest.approx(
-            lambda_max_estimate(P.S(level)), rel=1e-9)
+        # a mesh of its own: other tests set the estimate of shared meshes
+        P = Pair(name, level, 2 if level > 2 else level)
+        lg, lo = P.m.lambda_max(level), lambda_max_estimate(P.S(level))
+        print(f"{name} level {level}: lambda GPU {lg!r} oracle {lo!r} "
+              f"rel diff {abs(lg - lo) / lo:.2e}")
+        assert lg == pytest.approx(lo, rel=FP64_TOL)
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-5)])
+@pytest.mark.parametrize("dtype,tol", [("f64", FP64_TOL), ("f32", 1e-5)])
 @pytest.mark.parametrize("nu,degree", [((1, 1), 2), ((2, 1), 3)])
 def test_vcycle_chebyshev_iterates(dtype, tol, nu, degree):
     """V-cycles with the Chebyshev smoother: every iterate against the
-    oracle's."""
+    oracle's.  Both sides run with the oracle's eigenvalue estimates (the
+    estimates themselves are compared in test_lambda_max_matches_oracle),
+    so the iterates differ only by the rounding of the operator passes."""
+    from oracle.mg import lambda_max_estimate
     P = pair("jittered_288", 4, 2)
     S = P.S(4)
+    for lvl in (3, 4):
+        P.m.set_lambda_max(lvl, lambda_max_estimate(P.S(lvl)))
     b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     bg = P.to_gpu(4, b, tdt)

@@ -89,6 +89,21 @@ def test_mesh_errors(lib):
     with pytest.raises(ht.HytetError) as e:
         m.info(0)
     assert e.value.code == _lib.HT_ERR_LEVEL
+    # eigenvalue estimates set from outside: host call, checked arguments
+    m.set_lambda_max(2, 1.9)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(ht.HytetError) as e:
+            m.set_lambda_max(2, bad)
+        assert e.value.code == _lib.HT_ERR_ARG
+    with pytest.raises(ht.HytetError) as e:
+        m.set_lambda_max(4, 1.9)
+    assert e.value.code == _lib.HT_ERR_LEVEL
+    # tile rows: 0 selects the band kernel where its image fits
+    m.set_tile_rows(3, _lib.HT_F64, 0)
+    assert m.tile_rows(3, _lib.HT_F64) == 0
+    with pytest.raises(ht.HytetError) as e:
+        m.set_tile_rows(3, _lib.HT_F64, 5)
+    assert e.value.code == _lib.HT_ERR_ARG
 
 
 def _slot_local_index(m, level, keys, flags):
