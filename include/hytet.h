@@ -254,6 +254,22 @@ int ht_p2_unpack(ht_mesh* mesh, int level, int dtype, int m, int layout,
  * non-Dirichlet micro-vertices (synchronises the stream). */
 int ht_residual(ht_mesh* mesh, int level, int dtype, const void* u,
                 const void* b, void* r, double* norm, ht_stream stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): ht_residual
+ * with its scratch, the norm partials, in a fixed device array of the
+ * library (4 MiB per GPU, held until the process ends) instead of the
+ * mesh's buffers.  The norm, if norm_dev != NULL, is written to that DEVICE
+ * address (one FP64 value) without synchronising.  Allocates nothing, on
+ * the device or through any library routine.  Requires the mesh to be on
+ * the device already (any earlier device call puts it there):
+ * HT_ERR_STATE otherwise.  HT_ERR_ARG when the level's partials (one per
+ * stencil-kernel wave and exchange block, plus 256) exceed the array:
+ * 2^19 values, which covers the 288-cell box at level 8.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU race (order
+ * them on one stream).  Arguments and results otherwise as ht_residual. */
+int ht_residual_noalloc(ht_mesh* mesh, int level, int dtype, const void* u,
+                        const void* b, void* r, double* norm_dev,
+                        ht_stream stream);
 /* `sweeps` weighted Jacobi sweeps u <- u + omega D^-1 (b - A u). */
 int ht_smooth_jacobi(ht_mesh* mesh, int level, int dtype, double omega,
                      int sweeps, void* u, const void* b, ht_stream stream);

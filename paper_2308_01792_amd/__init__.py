@@ -261,6 +261,15 @@ class Mesh:
                                  _stream()))
         return nrm.value if want_norm else r
 
+    def residual_noalloc(self, level: int, u, b, r, norm_dev=None):
+        """ht_residual_noalloc: r = b - A u with the library's fixed scratch;
+        norm_dev: a one-element FP64 device tensor that receives ||r||_2,
+        or None."""
+        check(load().ht_residual_noalloc(
+            self._h, level, _dtype_code(u), _ptr(u), _ptr(b), _ptr(r),
+            _ptr(norm_dev) if norm_dev is not None else None, _stream()))
+        return r
+
     def smooth_jacobi(self, level: int, u, b, omega: float = 2.0 / 3.0,
                       sweeps: int = 1):
         check(load().ht_smooth_jacobi(self._h, level, _dtype_code(u),

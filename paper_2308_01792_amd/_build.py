@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhytet.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["mesh.cpp", "abi.cpp", "kernels.hip", "band.hip", "walk.hip",
-           "vcoef.hip", "p2.hip", "p2_host.cpp"]
+           "vcoef.hip", "p2.hip", "p2_host.cpp", "scratch.hip"]
 ARCH = os.environ.get("HYTET_ARCH", "gfx950")
 
 

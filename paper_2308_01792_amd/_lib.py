@@ -79,6 +79,7 @@ SIGNATURES = {
     "ht_assemble_divkgrad": (I, [P, I, I, P, P, P]),
     "ht_apply_stored": (I, [P, I, I, P, P, P, P]),
     "ht_residual": (I, [P, I, I, P, P, P, C.POINTER(D), P]),
+    "ht_residual_noalloc": (I, [P, I, I, P, P, P, P, P]),
     "ht_smooth_jacobi": (I, [P, I, I, D, I, P, P, P]),
     "ht_restrict": (I, [P, I, I, P, P, P]),
     "ht_prolongate_add": (I, [P, I, I, P, P, P]),

@@ -16,6 +16,7 @@
 #include "p2.hpp"
 #include "kernels.hpp"
 #include "band.hpp"
+#include "scratch.hpp"
 #include "vcoef.hpp"
 
 struct ht_mesh;
@@ -412,12 +413,19 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
 // OP_RESID32 and OP_JACOBI the norm of b - A x (x: the operand) lands in
 // m.d_scalar[slot] (device) when want_norm.  OP_RESID32 (FP64 only) delivers
 // the residual in the FP32 vector y32 and uses y as FP64 scratch.
+// Norm partials of one residual / Jacobi pass over R: one per stencil-kernel
+// wave plus one per exchange block.
+static int64_t pass_partials(ht_mesh* h, int level, int dtype, int op, const Range& R);
+
 static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
                     void* y, const void* b, double omega, hipStream_t s,
                     bool want_norm, int scalar_slot, const Range& R,
-                    void* y32 = nullptr) {
+                    void* y32 = nullptr, double* partials = nullptr,
+                    double* norm_dst = nullptr) {
   Mesh& m = h->m;
   if (R.empty()) return;
+  if (!partials) partials = m.d_partials;
+  if (!norm_dst) norm_dst = m.d_scalar + scalar_slot;
   const Shape sh = choose_shape(h, level, dtype, op);
   if (op == OP_APPLY && sh.J == 0) {
     {
@@ -435,6 +443,7 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
   }
   CellArgs ca = cell_args(h, level, dtype, sh, x, y, b, omega, R);
   ca.y32 = at_cell(y32, R.c0, level, HT_F32);
+  ca.partials = partials;
   {
     const bool res = op == OP_RESID || op == OP_RESID32;
     Prof p(h, op == OP_APPLY ? "cell_apply" : res ? "cell_residual" : "cell_jacobi", s);
@@ -442,7 +451,7 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
     check_launch();
   }
   ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
-                          m.d_partials + kCellWaves * ca.nblocks, R);
+                          partials + kCellWaves * ca.nblocks, R);
   if (op == OP_RESID || op == OP_RESID32) ea.u = x;
   ea.y32 = y32;
   if (ea.total > 0) {
@@ -453,9 +462,16 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
   if ((op == OP_RESID || op == OP_RESID32 || op == OP_JACOBI) && want_norm) {
     const int64_t cnt = kCellWaves * ca.nblocks + (ea.total + 255) / 256;
     Prof p(h, "norm_sum", s);
-    launch_sum_partials(m.d_partials, cnt, m.d_scalar + scalar_slot, true, s);
+    launch_sum_partials(partials, cnt, norm_dst, true, s);
     check_launch();
   }
+}
+
+static int64_t pass_partials(ht_mesh* h, int level, int dtype, int op, const Range& R) {
+  const Shape sh = choose_shape(h, level, dtype, op);
+  const CellArgs ca = cell_args(h, level, dtype, sh, nullptr, nullptr, nullptr, 0.0, R);
+  const ExchArgs ea = exch_args(h, level, nullptr, nullptr, nullptr, 0.0, nullptr, R);
+  return kCellWaves * ca.nblocks + (ea.total + 255) / 256;
 }
 
 static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
@@ -1538,6 +1554,41 @@ int ht_residual(ht_mesh* h, int level, int dtype, const void* u, const void* b,
     op_pass(h, level, dtype, OP_RESID, u, r, b, 0.0, s, norm != nullptr, 0);
     if (norm) *norm = read_scalar(h, 0, s);
   });
+}
+
+int ht_residual_noalloc(ht_mesh* h, int level, int dtype, const void* u,
+                        const void* b, void* r, double* norm_dev, ht_stream stream) {
+  // No std::function and no allocation on the success path: the checks,
+  // the scratch lookup and the launches only.
+  try {
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    check_level(h->m, level);
+    check_dtype(dtype);
+    if (!h->m.uploaded)
+      throw Error{HT_ERR_STATE, "the mesh is not on the device yet: call a device "
+                                "entry point (e.g. ht_apply) once before, since "
+                                "uploading it allocates"};
+    check_ptr(u, "u");
+    check_ptr(b, "b");
+    check_ptr(r, "r");
+    if (r == u || r == b) throw Error{HT_ERR_ARG, "r must not alias u or b"};
+    const Range R = full_range(h->m);
+    const int64_t need = pass_partials(h, level, dtype, OP_RESID, R) + 256;
+    if (need > kNoAllocScratch)
+      throw Error{HT_ERR_ARG, "level too large for the allocation-free residual: its norm "
+                              "partials need " + std::to_string(need) + " values, the "
+                              "scratch holds " + std::to_string((long long)kNoAllocScratch)};
+    double* p = noalloc_scratch();
+    op_pass(h, level, dtype, OP_RESID, u, r, b, 0.0, (hipStream_t)stream,
+            norm_dev != nullptr, 0, R, nullptr, p, norm_dev);
+    return HT_OK;
+  } catch (const Error& e) {
+    set_error(e.code, e.msg);
+    return e.code;
+  } catch (...) {
+    set_error(HT_ERR_ARG, "unknown error");
+    return HT_ERR_ARG;
+  }
 }
 
 int ht_smooth_jacobi(ht_mesh* h, int level, int dtype, double omega, int nsw,
