@@ -650,3 +650,20 @@ def test_row_oracle_with_coefficient_matches_assembly():
         assert dirichlet == bool(S.dirichlet[v])
         dense = S.A[v].toarray().ravel()
         assert np.abs(dense[mesh.index_of(nbr)] - vals).max() <= 1e-15
+
+
+def test_threaded_csr_product_equals_scipy():
+    """The CPU baseline's threaded CSR product (oracle/spmv.cpp) against
+    SciPy's product of the same assembled matrix, for several thread counts
+    (the row split must cover every row exactly once)."""
+    from oracle import spmv
+    if not os.path.exists(spmv.LIB):
+        spmv.build()
+    S = oracle_hierarchy("jittered_222", 3, 3)[3]
+    M = spmv.CSR(S.A)
+    x = np.random.default_rng(3).uniform(-1, 1, S.A.shape[0])
+    ref = S.A @ x
+    for threads in (1, 3, 8, 64):
+        y = np.full(S.A.shape[0], np.nan)
+        M.apply(x, y, threads)
+        assert np.array_equal(y, ref) or np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max()
