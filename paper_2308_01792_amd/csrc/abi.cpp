@@ -417,11 +417,17 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
 // wave plus one per exchange block.
 static int64_t pass_partials(ht_mesh* h, int level, int dtype, int op, const Range& R);
 
+// Extra output of the fused refinement pass (OP_RESID32X): the first
+// zero-guess sweep of the next correction.
+struct Fuse {
+  void* efirst = nullptr;
+};
+
 static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
                     void* y, const void* b, double omega, hipStream_t s,
                     bool want_norm, int scalar_slot, const Range& R,
                     void* y32 = nullptr, double* partials = nullptr,
-                    double* norm_dst = nullptr) {
+                    double* norm_dst = nullptr, const Fuse* fuse = nullptr) {
   Mesh& m = h->m;
   if (R.empty()) return;
   if (!partials) partials = m.d_partials;
@@ -444,22 +450,25 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
   CellArgs ca = cell_args(h, level, dtype, sh, x, y, b, omega, R);
   ca.y32 = at_cell(y32, R.c0, level, HT_F32);
   ca.partials = partials;
+  if (fuse) ca.efirst = at_cell(fuse->efirst, R.c0, level, HT_F32);
   {
-    const bool res = op == OP_RESID || op == OP_RESID32;
+    const bool res = op == OP_RESID || op == OP_RESID32 || op == OP_RESID32X;
     Prof p(h, op == OP_APPLY ? "cell_apply" : res ? "cell_residual" : "cell_jacobi", s);
     launch_cell(dtype, op, sh.J, ca, s);
     check_launch();
   }
   ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
                           partials + kCellWaves * ca.nblocks, R);
-  if (op == OP_RESID || op == OP_RESID32) ea.u = x;
+  if (op == OP_RESID || op == OP_RESID32 || op == OP_RESID32X) ea.u = x;
   ea.y32 = y32;
+  if (fuse) ea.efirst = fuse->efirst;
   if (ea.total > 0) {
     Prof p(h, "exchange", s);
     launch_exchange(dtype, op, ea, s);
     check_launch();
   }
-  if ((op == OP_RESID || op == OP_RESID32 || op == OP_JACOBI) && want_norm) {
+  if ((op == OP_RESID || op == OP_RESID32 || op == OP_RESID32X || op == OP_JACOBI) &&
+      want_norm) {
     const int64_t cnt = kCellWaves * ca.nblocks + (ea.total + 255) / 256;
     Prof p(h, "norm_sum", s);
     launch_sum_partials(partials, cnt, norm_dst, true, s);
@@ -1682,13 +1691,31 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
     LevelWork& w64 = work(h, level, HT_F64);
     const bool mixed = o->precision == HT_PREC_MIXED;
     LevelWork* w32 = mixed ? &work(h, level, HT_F32) : nullptr;
+    // Fused refinement (Jacobi smoother): the FP64 residual pass, which
+    // rounds the residual to FP32 as the next right-hand side, also writes
+    // the next correction's first zero-guess sweep (into ffirst), so the
+    // FP32 V-cycle starts after that sweep.  (Adding the correction to u
+    // inside the same pass was measured slower: the stencil kernel loads
+    // each row of u more than once, and every load would read e too.)
+    const bool fused = mixed && o->cyc.smoother == HT_SMOOTH_JACOBI && o->cyc.nu1 > 0;
+    void* ffirst = fused ? w32->t : nullptr;   // holds the first sweep
+    void* fother = fused ? w32->u : nullptr;
+    // the V-cycle started from a done first sweep in its t buffer ends in t
+    // after an even number of further sweeps
+    const bool e_in_t = ((o->cyc.nu1 - 1 + o->cyc.nu2) % 2) == 0;
     // residual of the initial iterate (mixed: delivered in FP32 as the
     // right-hand side of the first correction)
-    if (mixed)
+    if (fused) {
+      Fuse F;
+      F.efirst = ffirst;
+      op_pass(h, level, HT_F64, OP_RESID32X, u, w64.t, b, o->cyc.omega, s, true, 0,
+              full_range(h->m), w32->b, nullptr, nullptr, &F);
+    } else if (mixed) {
       op_pass(h, level, HT_F64, OP_RESID32, u, w64.t, b, 0.0, s, true, 0,
               full_range(h->m), w32->b);
-    else
+    } else {
       op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, s, true, 0);
+    }
     double rel = read_scalar(h, 0, s) * scale;
     st->res_history[0] = rel;
     int k = 0;
@@ -1711,7 +1738,17 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
         first_sweep(ss);
         return;
       }
-      if (!mixed) {
+      if (fused) {
+        void* e = vcycle_impl(h, level, HT_F32, o->cyc, fother, ffirst, w32->b, false,
+                              ss, true);
+        if (e != (e_in_t ? ffirst : fother))
+          throw Error{HT_ERR_STATE, "refinement: correction not in the expected buffer"};
+        flat(h, level, HT_F64, HT_F32, FOP_ADD, u, e, ss);
+        Fuse F;
+        F.efirst = e == w32->u ? w32->t : w32->u;
+        op_pass(h, level, HT_F64, OP_RESID32X, u, w64.t, b, o->cyc.omega, ss, true, 0,
+                full_range(h->m), w32->b, nullptr, nullptr, &F);
+      } else if (!mixed) {
         vcycle_top(h, level, HT_F64, o->cyc, u, b, false, ss);
         op_pass(h, level, HT_F64, OP_RESID, u, w64.t, b, 0.0, ss, true, 0);
       } else {
@@ -1741,8 +1778,19 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
       HT_CHECK_HIP(hipStreamSynchronize(s));
     }
     while (rel > o->rel_tol && k < o->max_cycles && std::isfinite(rel)) {
-      if (o->use_graph) run_graph(h, key.str(), step, s);
-      else step(s);
+      if (!fused) {
+        if (o->use_graph) run_graph(h, key.str(), step, s);
+        else step(s);
+      } else {
+        // the FP32 buffers' roles may alternate: one graph per assignment
+        std::ostringstream fk;
+        fk << key.str() << ':' << ffirst;
+        if (o->use_graph) run_graph(h, fk.str(), step, s);
+        else step(s);
+        void* e = e_in_t ? ffirst : fother;
+        ffirst = e == w32->u ? w32->t : w32->u;
+        fother = e;
+      }
       HT_CHECK_HIP(hipStreamSynchronize(s));
       rel = h->m.h_scalar[0] * scale;
       ++k;

@@ -174,10 +174,16 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
     }
   };
 
+  constexpr bool FUSE = (OP == OP_RESID32X);
+  constexpr bool R32 = (OP == OP_RESID32 || FUSE);
   constexpr bool NEED_B =
-      (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32 || OP == OP_CHEB);
+      (OP == OP_RESID || OP == OP_JACOBI || R32 || OP == OP_CHEB);
   const __amdgpu_buffer_rsrc_t ry32 = make_rsrc(
-      OP == OP_RESID32 ? (float*)a.y32 + cell * a.stride : (float*)a.y,
+      R32 ? (float*)a.y32 + cell * a.stride : (float*)a.y,
+      a.stride * (int64_t)sizeof(float));
+  // OP_RESID32X: the first sweep of the next correction
+  const __amdgpu_buffer_rsrc_t ref = make_rsrc(
+      FUSE ? (float*)a.efirst + cell * a.stride : (float*)a.y,
       a.stride * (int64_t)sizeof(float));
   double nsq = 0.0;
   // One plane step: compute plane k from (pm, pc, pp) = planes k-1, k, k+1
@@ -316,11 +322,17 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
           out = surf ? acc : c + dn;
           bstore(dn, rd, surf ? HT_OOB : so);
         }
-        if (OP == OP_RESID32) {
+        if (R32) {
           // finished points: FP32 residual (element offset = so / 2);
           // surface points: the FP64 partial row, completed by the exchange
           bstore((float)r, ry32, surf ? HT_OOB : so >> 1);
           bstore(acc, ry, surf ? so : HT_OOB);
+          if (FUSE) {
+            // the next correction's first sweep at the finished points, in
+            // FP32 as the separate zero-guess sweep forms it (the factor
+            // rounded to FP32 times the FP32 residual: bit for bit)
+            bstore((float)omega_invd * (float)r, ref, surf ? HT_OOB : so >> 1);
+          }
           continue;
         }
       }
@@ -462,7 +474,7 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       T val;
       if (P.boundary) {
         val = (OP == OP_JACOBI || OP == OP_CHEB) ? ((const T*)a.u)[s0] : (T)0;
-      } else if (OP == OP_RESID || OP == OP_RESID32) {
+      } else if (OP == OP_RESID || OP == OP_RESID32 || OP == OP_RESID32X) {
         val = ((const T*)a.b)[s0] - sum;
         nsq = (double)val * (double)val;
       } else if (OP == OP_JACOBI) {
@@ -482,17 +494,27 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       } else {
         val = sum;
       }
-      if (OP == OP_RESID32) {
+      if (OP == OP_RESID32 || OP == OP_RESID32X) {
         float* y32 = (float*)a.y32;
         y32[s0] = (float)val;
         for (int q = 1; q < cnt; ++q) y32[slot_q(q)] = (float)val;
+        if (OP == OP_RESID32X) {
+          // first zero-guess sweep of the next correction (0 on the
+          // Dirichlet boundary, where val is 0)
+          // (FP32 factor times FP32 residual, as the zero-guess sweep)
+          const float e = (float)(a.omega * a.nscale * P.inv_diag_unit) * (float)val;
+          float* ef = (float*)a.efirst;
+          ef[s0] = e;
+          for (int q = 1; q < cnt; ++q) ef[slot_q(q)] = e;
+        }
       } else {
         y[s0] = val;
         for (int q = 1; q < cnt; ++q) y[slot_q(q)] = val;
       }
     }
   }
-  if (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32 || OP == OP_CHEB) {
+  if (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32 || OP == OP_CHEB ||
+      OP == OP_RESID32X) {
     __shared__ double red[4];
     nsq = wave_sum(nsq);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nsq;
@@ -594,10 +616,12 @@ void launch_cell(int dtype, int op, int J, const CellArgs& a, hipStream_t s) {
     else if (op == OP_RESID) launch_cell_t<double, OP_RESID>(a, J, s);
     else if (op == OP_JACOBI) launch_cell_t<double, OP_JACOBI>(a, J, s);
     else if (op == OP_RESID32) launch_cell_t<double, OP_RESID32>(a, J, s);
+    else if (op == OP_RESID32X) launch_cell_t<double, OP_RESID32X>(a, J, s);
     else if (op == OP_CHEB) launch_cell_t<double, OP_CHEB>(a, J, s);
     else launch_cell_t<double, OP_RESTRICT>(a, J, s);
   } else {
-    if (op == OP_RESID32) throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input"};
+    if (op == OP_RESID32 || op == OP_RESID32X)
+      throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input"};
     if (op == OP_CHEB) { launch_cell_t<float, OP_CHEB>(a, J, s); return; }
     if (op == OP_APPLY) launch_cell_t<float, OP_APPLY>(a, J, s);
     else if (op == OP_RESID) launch_cell_t<float, OP_RESID>(a, J, s);
@@ -617,21 +641,26 @@ static void launch_exchange_t(int op, const ExchArgs& a, hipStream_t s) {
     case OP_FILL: hipLaunchKernelGGL((k_exchange<T, OP_FILL>), grid, dim3(256), 0, s, a); break;
     case OP_RESTRICT: hipLaunchKernelGGL((k_exchange<T, OP_RESTRICT>), grid, dim3(256), 0, s, a); break;
     case OP_RESID32: hipLaunchKernelGGL((k_exchange<T, OP_RESID32>), grid, dim3(256), 0, s, a); break;
+    case OP_RESID32X: hipLaunchKernelGGL((k_exchange<T, OP_RESID32X>), grid, dim3(256), 0, s, a); break;
     case OP_CHEB: hipLaunchKernelGGL((k_exchange<T, OP_CHEB>), grid, dim3(256), 0, s, a); break;
   }
 }
 void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
   if (a.total <= 0) return;
   if (op != OP_APPLY && op != OP_RESID && op != OP_JACOBI && op != OP_SYNC &&
-      op != OP_FILL && op != OP_RESTRICT && op != OP_RESID32 && op != OP_CHEB)
+      op != OP_FILL && op != OP_RESTRICT && op != OP_RESID32 && op != OP_CHEB &&
+      op != OP_RESID32X)
     throw Error{HT_ERR_ARG, "unknown exchange operation"};
   // the residual and Jacobi epilogues read u and b at the owner copy
-  if ((op == OP_RESID || op == OP_JACOBI || op == OP_RESID32 || op == OP_CHEB) &&
+  if ((op == OP_RESID || op == OP_JACOBI || op == OP_RESID32 || op == OP_CHEB ||
+       op == OP_RESID32X) &&
       (!a.u || !a.b))
     throw Error{HT_ERR_ARG, "exchange for residual/Jacobi needs u and b"};
   if (op == OP_CHEB && !a.d) throw Error{HT_ERR_ARG, "Chebyshev step needs d"};
-  if (op == OP_RESID32 && (dtype != HT_F64 || !a.y32))
+  if ((op == OP_RESID32 || op == OP_RESID32X) && (dtype != HT_F64 || !a.y32))
     throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input and y32"};
+  if (op == OP_RESID32X && !a.efirst)
+    throw Error{HT_ERR_ARG, "fused refinement pass needs the first-sweep output"};
   if (dtype == HT_F64) launch_exchange_t<double>(op, a, s);
   else launch_exchange_t<float>(op, a, s);
 }

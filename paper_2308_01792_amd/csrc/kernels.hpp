@@ -13,8 +13,11 @@ namespace ht {
 // y32.
 // OP_CHEB: one step of the Chebyshev iteration on D^-1 A:
 // d <- c1 d + c2 D^-1 (b - A x) (in place), y = x + d.
+// OP_RESID32X: OP_RESID32 plus the first zero-guess Jacobi sweep
+// omega D^-1 r of the next FP32 correction (efirst), so that iterative
+// refinement needs no separate pass for that sweep.
 enum { OP_APPLY = 0, OP_RESID = 1, OP_JACOBI = 2, OP_SYNC = 3, OP_FILL = 4,
-       OP_RESTRICT = 5, OP_RESID32 = 6, OP_CHEB = 7 };
+       OP_RESTRICT = 5, OP_RESID32 = 6, OP_CHEB = 7, OP_RESID32X = 8 };
 enum { EOP_ZERO_GUESS = 0, EOP_MASS = 1, EOP_ZERO_INTERIOR = 2, EOP_DOT = 3,
        EOP_FLAGS = 4, EOP_COORDS = 5, EOP_PROBE = 6 };
 enum { FOP_COPY = 0, FOP_ADD = 1, FOP_ZERO = 2 };
@@ -29,13 +32,15 @@ enum { kCellWaves = HT_CELL_WAVES };
 // residual, Chebyshev step); their tile shape is chosen separately from the
 // apply's.
 constexpr bool op_is_sweep(int op) {
-  return op == OP_RESID || op == OP_JACOBI || op == OP_RESID32 || op == OP_CHEB;
+  return op == OP_RESID || op == OP_JACOBI || op == OP_RESID32 || op == OP_CHEB ||
+         op == OP_RESID32X;
 }
 
 struct CellArgs {
   const void* x;        // operand (u for residual / Jacobi)
   void* y;              // output
-  void* y32;            // FP32 residual (OP_RESID32)
+  void* y32;            // FP32 residual (OP_RESID32, OP_RESID32X)
+  void* efirst;         // OP_RESID32X: omega D^-1 r in FP32
   void* d;              // Chebyshev direction (OP_CHEB), updated in place
   double c1, c2;        // Chebyshev step coefficients
   const void* b;        // right-hand side (residual / Jacobi)
@@ -57,7 +62,8 @@ struct CellArgs {
 
 struct ExchArgs {
   void* y;
-  void* y32;            // FP32 residual (OP_RESID32)
+  void* y32;            // FP32 residual (OP_RESID32, OP_RESID32X)
+  void* efirst;         // OP_RESID32X: omega D^-1 r in FP32
   void* d;              // Chebyshev direction (OP_CHEB)
   double c1, c2;
   const void* u;
