@@ -75,7 +75,7 @@ def measured_traffic(kernel: str):
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "device.hpp"):
+    for f in ("kernels.hip", "kernels.hpp", "device.hpp", "band.hip", "band.hpp"):
         with open(os.path.join(ROOT, "paper_2308_01792_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if rec.get("sources_sha256") != h.hexdigest() or rec.get("kernel") != kernel:
@@ -426,7 +426,8 @@ def main():
     ms32 = e0.elapsed_time(e1) / args.steps
     del x32, y32
 
-    kname = f"k_cell<double, 0, {rows64}>"
+    # tile rows 0 selects the band kernel (LDS-staged planes)
+    kname = "k_band<double, 0>" if rows64 == 0 else f"k_cell<double, 0, {rows64}>"
     traffic = measured_traffic(kname)
     out = {
         "metric": "GDoF/s of matrix-free P1 apply + %HBM roofline; V-cycle "

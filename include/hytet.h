@@ -164,7 +164,13 @@ int ht_p2_offsets(int* len, int* d);
 int ht_p2_stencils(const ht_mesh* mesh, int level, double* out);
 
 /* ------------------------------------------------------- vector ops ---- */
-/* Make a vector consistent: every copy takes its owner's value. */
+/* Make a vector consistent: every copy takes its owner's value.
+ * Section 2 (domain partitioning): each coarse-mesh primitive owns the data
+ * of its interior points, and a point on a shared face, edge or vertex is
+ * held once by its owning primitive and as a copy by every macro-cell that
+ * touches it; this is the exchange from owners to copies.  Works in place on
+ * v (n_slots elements of dtype, device memory); asynchronous on `stream`;
+ * HT_ERR_LEVEL for a level outside the mesh's range. */
 int ht_sync(ht_mesh* mesh, int level, int dtype, void* v, ht_stream stream);
 /* Set all Dirichlet slots to `value` (all copies). */
 int ht_fill_dirichlet(ht_mesh* mesh, int level, int dtype, void* v,
@@ -251,7 +257,14 @@ int ht_p2_pack(ht_mesh* mesh, int level, int dtype, int m, int layout,
 int ht_p2_unpack(ht_mesh* mesh, int level, int dtype, int m, int layout,
                  const void* arrays, void* lattice, ht_stream stream);
 /* r = b - A u (0 at Dirichlet); if norm != NULL, also ||r||_2 over unique
- * non-Dirichlet micro-vertices (synchronises the stream). */
+ * non-Dirichlet micro-vertices (synchronises the stream).
+ * Section 5.2 (operator design): iterative solvers need only the action of
+ * the operator on a vector; the residual is that action (the stencil apply
+ * of Section 5.2.2) subtracted from the right-hand side in the same pass.
+ * u, b: consistent inputs, r: output, each n_slots elements of dtype in
+ * device memory; r must not alias u.  Dirichlet values of u act as data.
+ * Asynchronous unless norm != NULL; HT_ERR_LEVEL / HT_ERR_ARG on a bad level
+ * or dtype. */
 int ht_residual(ht_mesh* mesh, int level, int dtype, const void* u,
                 const void* b, void* r, double* norm, ht_stream stream);
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -270,27 +283,68 @@ int ht_residual(ht_mesh* mesh, int level, int dtype, const void* u,
 int ht_residual_noalloc(ht_mesh* mesh, int level, int dtype, const void* u,
                         const void* b, void* r, double* norm_dev,
                         ht_stream stream);
-/* `sweeps` weighted Jacobi sweeps u <- u + omega D^-1 (b - A u). */
+/* `sweeps` weighted Jacobi sweeps u <- u + omega D^-1 (b - A u).
+ * Section 5.2.1: smoothers that need only operator applications and the
+ * diagonal suit matrix-free operators (Jacobi, and its Chebyshev
+ * acceleration); the diagonal is the stencil's centre weight of Section
+ * 5.2.2.  u is updated in place (consistent on exit); b is read; both
+ * n_slots elements of dtype in device memory; Dirichlet values of u are
+ * kept.  sweeps >= 0 (HT_ERR_ARG otherwise); asynchronous on `stream`. */
 int ht_smooth_jacobi(ht_mesh* mesh, int level, int dtype, double omega,
                      int sweeps, void* u, const void* b, ht_stream stream);
 /* r_coarse = P^T r_fine (Dirichlet entries of r_fine taken as zero, coarse
- * Dirichlet entries set to zero); P = nested P1 interpolation. */
+ * Dirichlet entries set to zero); P = nested P1 interpolation.
+ * Section 5.1: a function holds a coefficient vector on every level of the
+ * hierarchy, and the regular refinement of Section 3.1 nests the P1 spaces,
+ * so the transfer operators of geometric multigrid are fixed by the mesh.
+ * r_fine: n_slots(fine_level) elements, r_coarse: n_slots(fine_level - 1)
+ * elements, both dtype in device memory; the output is consistent.
+ * HT_ERR_LEVEL unless min_level < fine_level <= max_level. */
 int ht_restrict(ht_mesh* mesh, int fine_level, int dtype, const void* r_fine,
                 void* r_coarse, ht_stream stream);
-/* u_fine += P e_coarse (Dirichlet entries of e_coarse taken as zero). */
+/* u_fine += P e_coarse (Dirichlet entries of e_coarse taken as zero).
+ * The prolongation of Section 5.1's level hierarchy (P1 interpolation on
+ * the refinement of Section 3.1): a new point is the midpoint of a coarse
+ * micro-edge and takes the mean of the edge's end values.  e_coarse:
+ * n_slots(coarse_level), u_fine: n_slots(coarse_level + 1) elements of
+ * dtype in device memory, u_fine updated in place (consistent on exit).
+ * HT_ERR_LEVEL unless min_level <= coarse_level < max_level. */
 int ht_prolongate_add(ht_mesh* mesh, int coarse_level, int dtype,
                       const void* e_coarse, void* u_fine, ht_stream stream);
 /* Exact solve of the interior equations at `level` (dense Cholesky inverse
- * computed on the host at first use), Dirichlet values of u kept. */
+ * computed on the host at first use), Dirichlet values of u kept.
+ * The coarsest level of a multigrid hierarchy (Section 5.1; the paper's
+ * remark on the minimum refinement level, Section 3.2, puts it at level 2
+ * or above, where every micro-primitive subgroup exists).  b read, u
+ * written: n_slots elements of dtype in device memory.  The library keeps
+ * the inverse (FP64,
+ * one dense block per problem of a batch mesh) per level, so the coarse
+ * level must stay small (its memory grows with the square of its unknowns);
+ * HT_ERR_MESH if the interior matrix is not positive definite, HT_ERR_LEVEL
+ * outside the mesh's range. */
 int ht_coarse_solve(ht_mesh* mesh, int level, int dtype, const void* b,
                     void* u, ht_stream stream);
-/* One V(nu1, nu2) cycle for A u = b at `level` down to opts->coarse_level. */
+/* One V(nu1, nu2) cycle for A u = b at `level` down to opts->coarse_level.
+ * Section 6 runs its solvers as V(1,1) cycles inside full multigrid; the
+ * cycle here is the textbook one built from the calls above: nu1 smoothing
+ * sweeps, residual, restriction, the cycle (or the coarse solve) one level
+ * down from a zero guess, prolongation of the correction, nu2 sweeps.
+ * u updated in place, b read: n_slots(level) elements of dtype in device
+ * memory, consistent.  The library keeps per-level work vectors and may
+ * replay the cycle from a captured HIP graph.  HT_ERR_ARG for negative
+ * sweep counts or coarse_level outside [min_level, level]. */
 int ht_vcycle(ht_mesh* mesh, int level, int dtype, const ht_cycle_opts* opts,
               void* u, const void* b, ht_stream stream);
 /* Solve A u = b (u, b: HT_F64 vectors) from the given u.  HT_PREC_F64 runs
  * FP64 V-cycles; HT_PREC_MIXED runs FP32 V-cycles inside FP64 iterative
  * refinement (FP64 residual, FP64 update, FP64 coarse solve).  Synchronises
- * once per cycle to read the residual norm. */
+ * once per cycle to read the residual norm.
+ * Repeats the V-cycle of Section 6's solvers until the relative residual
+ * ||b - A u|| / ||b|| falls below opts->rel_tol, or opts->max_cycles
+ * cycles have run (HT_ERR_NOT_CONVERGED, u holds the last iterate).  u
+ * updated in place, b read: n_slots(level) FP64 elements in device memory;
+ * stats (host, may be NULL) receives the cycle count, final relative
+ * residual, wall time and residual history. */
 int ht_solve(ht_mesh* mesh, int level, const ht_solve_opts* opts, void* u,
              const void* b, ht_solve_stats* stats, ht_stream stream);
 

@@ -66,5 +66,67 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host sources: their CPU code (mesh set-up, layouts, stencils, the C ABI's
+# argument checks) is what the sanitized variant instruments.
+HOST_SOURCES = ["mesh.cpp", "abi.cpp", "p2_host.cpp"]
+SANITIZED = os.path.join(BUILD, "san", "libhytet_san.so")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """libhytet with AddressSanitizer and UndefinedBehaviorSanitizer on its
+    host code (device code is built as usual): the host sources are rebuilt
+    instrumented and linked with the regular device objects, which build()
+    must have produced.  Load it with clang's ASan runtime preloaded."""
+    san_dir = os.path.dirname(SANITIZED)
+    os.makedirs(san_dir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+    flags = [f for f in _flags() if f != "-O3"] + ["-O1", "-g"] + san
+
+    def one(src: str) -> str:
+        obj = os.path.join(san_dir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"compiling {src} (sanitized) failed:\n{res.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(HOST_SOURCES)) as ex:
+        objs = list(ex.map(one, HOST_SOURCES))
+    dev = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o")
+           for s in SOURCES if s not in HOST_SOURCES]
+    missing = [o for o in dev if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"device objects missing (run build() first): {missing}")
+    tmp = SANITIZED + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] \
+        + san + ["-shared-libsan"] + objs + dev + ["-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"linking the sanitized library failed:\n{res.stderr}")
+    os.replace(tmp, SANITIZED)
+    return SANITIZED
+
+
+def asan_runtime() -> str:
+    """Path of clang's shared ASan runtime (to preload into a host process
+    that loads the sanitized library)."""
+    res = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True)
+    path = res.stdout.strip()
+    if res.returncode == 0 and os.path.isabs(path) and os.path.exists(path):
+        return path
+    import glob
+    cands = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not cands:
+        raise RuntimeError("clang's ASan runtime not found")
+    return cands[-1]
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    if "--sanitized" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))

@@ -5,7 +5,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhytet.so")
+# HYTET_LIB names another build of the library (the sanitized host build
+# used by the CPU tests); the default is the in-tree one.
+LIB_PATH = os.environ.get("HYTET_LIB") or os.path.join(HERE, "libhytet.so")
 
 HT_OK, HT_ERR_ARG, HT_ERR_MESH, HT_ERR_LEVEL, HT_ERR_OOM, HT_ERR_HIP, \
     HT_ERR_NOT_CONVERGED, HT_ERR_STATE = range(8)
