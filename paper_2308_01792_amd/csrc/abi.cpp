@@ -52,6 +52,8 @@ struct ht_mesh {
   // (level, dtype) -> band-kernel work items of one cell (absent where no
   // band fits the LDS image capacity)
   std::map<std::pair<int, int>, std::pair<int2*, int64_t>> band_items;
+  // (level, dtype) -> the band kernel's row table (make_band_rowtab)
+  std::map<std::pair<int, int>, uint8_t*> band_rowtab;
   // (level, dtype) -> (J, waves side by side in i) of the sweep operations
   std::map<std::pair<int, int>, std::pair<int, bool>> tuned_sweep;
   std::map<int, double> lambda_max;            // level -> estimate
@@ -250,8 +252,12 @@ void ensure_uploaded_h(ht_mesh* h) {
     }
     for (int dt : {HT_F64, HT_F32}) {
       std::vector<int2> it;
-      if (make_band_items(1 << l, band_cap(dt == HT_F64), kBandMinRows, it))
+      if (make_band_items(1 << l, band_cap(dt == HT_F64), kBandMinRows, it)) {
         h->band_items[{l, dt}] = {upload(it), (int64_t)it.size()};
+        std::vector<uint8_t> tab;
+        make_band_rowtab(l, band_cap(dt == HT_F64), (int)esize(dt), it, tab);
+        h->band_rowtab[{l, dt}] = upload(tab);
+      }
     }
     pcap = std::max(pcap, partials_needed(h, l));
   }
@@ -312,7 +318,7 @@ static bool has_band(const ht_mesh* h, int level, int dtype) {
 static int choose_J(ht_mesh* h, int level, int dtype) {
   auto it = h->tuned_J.find({level, dtype});
   if (it != h->tuned_J.end()) return it->second;
-  return dtype == HT_F64 && has_band(h, level, dtype) ? 0 : kDefaultJ;
+  return has_band(h, level, dtype) ? 0 : kDefaultJ;
 }
 
 // Tile shape of a stencil launch: rows per wave and wave arrangement.  The
@@ -375,6 +381,7 @@ static BandArgs band_args(ht_mesh* h, int level, int dtype, const void* x, void*
   a.w = (const char*)level_weights(h, level, dtype) + R.c0 * 240 * (int64_t)esize(dtype);
   const auto& it = h->band_items.at({level, dtype});
   a.items = it.first;
+  a.rtab = h->band_rowtab.at({level, dtype});
   a.nitems = it.second;
   a.nblocks = (R.c1 - R.c0) * it.second;
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
@@ -1223,6 +1230,7 @@ int ht_mesh_destroy(ht_mesh* h) {
       for (auto& kv : h->tiles) (void)hipFree(kv.second.first);
       for (auto& kv : h->walk_tiles) (void)hipFree(kv.second.first);
       for (auto& kv : h->band_items) (void)hipFree(kv.second.first);
+      for (auto& kv : h->band_rowtab) (void)hipFree(kv.second);
       for (auto* p : m.d_w64) if (p) (void)hipFree(p);
       for (auto* p : m.d_w32) if (p) (void)hipFree(p);
       for (auto* p : m.d_kc64) if (p) (void)hipFree(p);

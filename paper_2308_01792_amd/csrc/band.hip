@@ -7,10 +7,12 @@
 // and stores touch short, unaligned pieces of several rows.  Here a
 // workgroup owns a band of whole rows of one cell, and
 //   * loads each plane of the band once, as one contiguous run of the main
-//     block plus the band's face entries, into an LDS image (band.hpp);
-//   * assigns each lane two consecutive image positions, so a wave's 124
-//     outputs are consecutive closure points, possibly spanning several
-//     rows, and its stores form one contiguous run of the main block;
+//     block in 16-byte vectors plus the band's face entries, into an LDS
+//     image (band.hpp), each value's image row coming from a per-level
+//     table shared by all cells;
+//   * gives each lane a 2 x 2 block of outputs: two consecutive points of
+//     two consecutive rows, which share four of their seven neighbour rows,
+//     so ten paired LDS reads serve four points;
 //   * keeps a four-plane ring in LDS (planes k - 1, k, k + 1 are read while
 //     plane k + 2 is written) and four more planes in flight from HBM.
 // The workgroup's waves are split by role: four load waves stream the band's
@@ -43,21 +45,23 @@ __device__ __forceinline__ int bstart(int r, int L0) {
   return __mul24(r, L0 + 2) - (__mul24(r, r - 1) >> 1);
 }
 
-// Image row of position U, 0 <= U < D(rows), rows <= L0 + 1: the largest r
-// with D(r) <= U, i.e. the floor of the smaller root t of D(r) = U.  The
-// radicand and its terms are integers below 2^24, exact in FP32, and the
-// hardware square root is within 1 ulp, so t is known to within 5e-4; the
-// estimate biased down by 1e-3 is floor(t) or floor(t) - 1, and one
-// comparison settles which.  Returns r and D(r).
-__device__ __forceinline__ int brow(int U, int L0, int& Dr) {
-  const float b = (float)(2 * L0 + 5);
-  const float x = fmaxf(fmaf(-8.0f, (float)U, b * b), 0.0f);
-  int r = (int)fmaf(b - __builtin_amdgcn_sqrtf(x), 0.5f, -1e-3f);
-  r = r < 0 ? 0 : r;
-  const int d0 = bstart(r, L0), d1 = d0 + (L0 - r) + 2;  // D(r), D(r + 1)
-  const bool up = d1 <= U;
-  Dr = up ? d1 : d0;
-  return up ? r + 1 : r;
+// Pair index of position u in the concatenation of the first rows of the
+// output row pairs: the largest p with E(p) = p b - p^2 <= u (b = L0 + 2),
+// i.e. the floor of the smaller root (b - sqrt(b^2 - 4 u)) / 2.  The radicand
+// is an integer below 2^24, exact in FP32, and the hardware square root is
+// within 1 ulp; the root estimate biased down by 1e-3 is then floor(p) or
+// floor(p) - 1 (checked exhaustively for every b up to 1100 with the square
+// root off by one ulp either way), and one comparison settles which.
+// Returns p and E(p).
+__device__ __forceinline__ int bpair(int u, int b, int& Ep) {
+  const float bf = (float)b;
+  const float x = fmaxf(fmaf(-4.0f, (float)u, bf * bf), 0.0f);
+  const int p = (int)fmaf(bf - __builtin_amdgcn_sqrtf(x), 0.5f, -1e-3f);
+  const int e0 = __mul24(p, b - p);
+  const int e1 = e0 + b - 2 * p - 1;  // E(p + 1)
+  const bool up = e1 <= u;
+  Ep = up ? e1 : e0;
+  return up ? p + 1 : p;
 }
 
 // Workgroup barrier that orders LDS accesses only.  __syncthreads() also
@@ -70,21 +74,31 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 template <typename T, int OP>
-__global__ __launch_bounds__(kBandThreads) void k_band(BandArgs a) {
+__global__ __launch_bounds__(kBandThreads)
+__attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
   constexpr int CAP = BandCap<T>::value;
   constexpr int NL = CAP / kBandLoadLanes;  // image values per load lane
   constexpr int PD = kBandDepth;            // planes in flight per load lane
-  __shared__ T ring[kBandSlots * CAP];
+  // the ring plus a pad that the reads of unused lanes may reach
+  __shared__ T ring[kBandSlots * CAP + kBandPad];
   __shared__ T wtab[16 * 15];
-  // XCD-aware block order: block b runs on XCD b % 8; each XCD gets a
-  // contiguous run of (cell, item) work, so concurrent bands of one cell
-  // share an L2.
+  // XCD-aware block order: block b runs on XCD b % 8, and each XCD gets a
+  // contiguous run of the work order.  That order takes the cells in groups
+  // of kGroup and, inside a group, item by item over its cells, so the
+  // neighbouring bands of each cell (whose halo rows and planes overlap)
+  // run close together in time on one XCD and share its L2.
+  constexpr int kGroup = 8;
   const int64_t nb = a.nblocks;
   const int64_t chunk = (nb + 7) / 8;
   const int64_t wb = (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
   if (wb >= nb) return;
-  const int64_t cell = wb / a.nitems;
-  const int2 it = a.items[wb % a.nitems];
+  const int64_t ncell = nb / a.nitems;
+  const int64_t per = (int64_t)kGroup * a.nitems;
+  const int64_t g = wb / per, rem = wb - g * per;
+  const int64_t gc = ncell - g * kGroup < kGroup ? ncell - g * kGroup : kGroup;
+  const int64_t item = rem / gc;
+  const int64_t cell = g * kGroup + (rem - item * gc);
+  const int2 it = a.items[item];
   const int j0 = it.x & 0xffff, R = it.x >> 16, k0 = it.y & 0xffff, k1 = it.y >> 16;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -98,100 +112,124 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandArgs a) {
 
   if (wave >= kBandComputeWaves) {
     // ---------------------------------------------------- load waves --
-    // Plane q of the band: load lane t holds image positions t + m kBandLoadLanes.
-    // Row r of the image is closure row jm + r: its first point (i = 0) is
-    // in S0, its last (i = e) in S1, the others in the main block, where
-    // consecutive rows follow each other (the main-block element of image
-    // position U in row r is mq + U - 4 r).  Every plane issues the same
-    // NL loads per lane (out-of-range ones return zero without touching
-    // memory), so the wait for the oldest plane is a fixed count.
+    // Plane q of the band.  Row r of its image is closure row jm + r: the
+    // row's first point (i = 0) is in S0, its last (i = e) in S1, the others
+    // in the main block, where consecutive rows follow each other: the main
+    // points of the image rows form one contiguous run of the cell block
+    // (band_plane).  Load lanes read that run in 16-byte vectors (V values
+    // each) and place every value at image position f + 4 r, the row r of
+    // run element f coming from the level's row table (band.hpp), which is
+    // read with the data; 64 lanes of two waves read the rows' two end
+    // points.  The address unit handles a fixed number of lanes per cycle,
+    // so few wide loads beat one load per image position.  Every plane
+    // issues the same loads per lane (out-of-range ones return zero without
+    // touching memory), so the wait for the oldest plane is a fixed count.
+    constexpr int V = 16 / (int)sizeof(T);
+    constexpr int NM = band_nm(CAP, V);
+    constexpr int TB = band_tb(NM * V);
+    typedef typename std::conditional<TB == 8, u32x2, u32x4>::type TabT;
     const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
     const int lw = wave - kBandComputeWaves;
-    T buf[PD][NL];
-    // Row of each held position and the start of that row, at the last
-    // plane issued.  From one plane to the next every row loses one point,
-    // so a position moves down by at most one row as long as the rows stay
-    // longer than the row indices (L0 > 2 R + 1); below that, and at the
-    // first plane, the row comes from the closed form.
-    int rs[NL], ds[NL];
+    const int lpos = lw * 64 + lane;
+    // each load lane's own discard position in the ring's pad (values there
+    // are never used)
+    const int discard = kBandSlots * CAP + (lpos & (kBandPad - 1));
+    u32x4 buf[PD][NM];  // main-run vectors of the planes in flight
+    T eb[PD];           // end point of each plane in flight
+    TabT tr[PD];        // row-table entries of the planes in flight
+    int fas[PD];        // run start fa of the planes in flight (uniform)
+    auto issue = [&](int q, u32x4 (&b)[NM], T& e, TabT& t, int& fa) {
+      const BandPlane P = band_plane(n, off_s0, off_s1, jm, R, k1, q, V);
+      fa = P.fa;
 #pragma unroll
-    for (int m = 0; m < NL; ++m) rs[m] = ds[m] = 0;
-    const int qfirst = k0 > 0 ? k0 - 1 : 0;
-    auto issue = [&](int q, T (&b)[NL]) {
-      const int L0 = n - jm - q + 1;
-      const int rows = (L0 < 0 || q > k1) ? 0 : (R + 2 < L0 + 1 ? R + 2 : L0 + 1);
-      const int size = bstart(rows, L0);
-      const bool plane_ok = q >= 0 && q <= n;
-      const bool incr = q > qfirst && L0 > 2 * R + 1;
-      const int s0b = off_s0 + tri32(n + 1) - tri32(n + 1 - q) + jm;
-      const int s1b = off_s1 + tri32(n) - tri32(n - q) + jm;
-      const int mq = tet32(n - 1) - tet32(n - 1 - q) - 2 + jm * (n - 1 - q) -
-                     ((jm * (jm - 1)) >> 1);
-#pragma unroll
-      for (int m = 0; m < NL; ++m) {
-        const int U0 = m * kBandLoadLanes + lw * 64;
-        unsigned off = HT_OOB;
-        if (plane_ok && U0 < size) {  // uniform
-          const int U = U0 + lane;
-          int r, Dr;
-          if (incr) {
-            r = rs[m];
-            Dr = ds[m] - r;
-            const int nx = Dr + (L0 - r) + 2;
-            const bool up = U >= nx;
-            r += up ? 1 : 0;
-            Dr = up ? nx : Dr;
-          } else {
-            r = brow(U < size ? U : size - 1, L0, Dr);
-          }
-          rs[m] = r;
-          ds[m] = Dr;
-          const int c = U - Dr, Lr = L0 - r;
-          const bool end = c == 1 || c == Lr;
-          const int el = end ? (c == 1 ? s0b : s1b) + r : mq + U - 4 * r;
-          const bool data = jm + r >= 0 && c >= 1 && c <= Lr && U < size;
-          off = data ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB;
-        }
-        bload(b[m], rx, off);
+      for (int m = 0; m < NM; ++m) {
+        const int f = P.fa + V * (lpos + kBandLoadLanes * m);
+        const bool ok = (f + V > P.F0) & (f < P.F1);
+        b[m] = __builtin_amdgcn_raw_buffer_load_b128(
+            rx, ok ? (unsigned)(P.mq + f) * (unsigned)sizeof(T) : HT_OOB, 0, 0);
       }
+      const int qr = q - (k0 - 1);
+      const int64_t blk = (P.valid && qr < kBandTabPlanes) ? 1 + item * kBandTabPlanes + qr : 0;
+      const __amdgpu_buffer_rsrc_t rt =
+          make_rsrc(a.rtab + blk * (kBandLoadLanes * TB), kBandLoadLanes * TB);
+      if constexpr (TB == 8)
+        t = __builtin_amdgcn_raw_buffer_load_b64(rt, (unsigned)(lpos * TB), 0, 0);
+      else
+        t = __builtin_amdgcn_raw_buffer_load_b128(rt, (unsigned)(lpos * TB), 0, 0);
+      // lanes 0 .. 63: S0 point of row lpos; lanes 64 .. 127: S1 point of
+      // row lpos - 64
+      const int r = lpos & 63, Lr = P.L0 - r;
+      const bool side = lpos >= 64;
+      const bool eok = (lpos < 128) & (r < P.rows) & (jm + r >= 0) &
+                       (side ? Lr >= 2 : Lr >= 1);
+      const int el = (side ? P.s1b : P.s0b) + r;
+      bload(e, rx, eok ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB);
     };
-    // Every held value is written, past the image end too (those slot
-    // positions are never read as data): each register set is then consumed
-    // in full before it is reloaded, and the wait for it counts only the
-    // younger planes' loads.
-    auto commit = [&](int q, const T (&b)[NL]) {
+    auto commit = [&](int q, const u32x4 (&b)[NM], const T e, const TabT& t, const int fa) {
+      // the plane's validity and rows (as band_plane has them)
+      const int L0 = n - jm - q + 1;
+      const bool valid = q >= 0 && q <= n && q <= k1 && L0 >= 0;
+      const int rows = valid ? (R + 2 < L0 + 1 ? R + 2 : L0 + 1) : 0;
       T* s = ring + slot(q);
+      if ((q < 0 || q > n) && q <= k1) {  // outside the cell: zeros
+        for (int u = lpos; u < CAP; u += kBandLoadLanes) s[u] = (T)0;
+        return;
+      }
+      if (!valid) return;  // past the march: no later step reads it
+      const int base = slot(q);
 #pragma unroll
-      for (int m = 0; m < NL; ++m) s[m * kBandLoadLanes + lw * 64 + lane] = b[m];
+      for (int m = 0; m < NM; ++m) {
+        const int f = fa + V * (lpos + kBandLoadLanes * m);
+        const T* v = reinterpret_cast<const T*>(&b[m]);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const int w = m * V + i;  // byte w of the lane's table entry
+          const unsigned r4 = (t[w >> 2] >> (8 * (w & 3))) & 0xffu;
+          ring[r4 != 0xffu ? base + f + i + (int)r4 : discard] = v[i];
+        }
+      }
+      // pads and end points of the rows
+      const int r = lpos & 63;
+      if ((lpos < 128) & (r < rows)) {
+        const int D = bstart(r, L0), Lr = L0 - r;
+        if (lpos < 64) {
+          s[D] = (T)0;
+          s[D + 1] = e;
+        } else {
+          if (Lr >= 2) s[D + Lr] = e;
+          s[D + Lr + 1] = (T)0;
+        }
+      }
+      // the row j = -1 of the bands at j0 = 0 reads as zeros
+      if (jm < 0)
+        for (int u = 2 + lpos; u < L0; u += kBandLoadLanes) s[u] = (T)0;
     };
     // plane q travels in register set (q - k0 + 1) % PD
     static_assert(PD == 4, "the prologue below assumes four planes in flight");
-    issue(k0 - 1, buf[0]);
-    issue(k0, buf[1]);
-    issue(k0 + 1, buf[2]);
-    issue(k0 + 2, buf[3]);
-    commit(k0 - 1, buf[0]);
-    issue(k0 + 3, buf[0]);
-    commit(k0, buf[1]);
-    issue(k0 + 4, buf[1]);
-    commit(k0 + 1, buf[2]);
-    issue(k0 + 5, buf[2]);
+    issue(k0 - 1, buf[0], eb[0], tr[0], fas[0]);
+    issue(k0, buf[1], eb[1], tr[1], fas[1]);
+    issue(k0 + 1, buf[2], eb[2], tr[2], fas[2]);
+    issue(k0 + 2, buf[3], eb[3], tr[3], fas[3]);
+    commit(k0 - 1, buf[0], eb[0], tr[0], fas[0]);
+    issue(k0 + 3, buf[0], eb[0], tr[0], fas[0]);
+    commit(k0, buf[1], eb[1], tr[1], fas[1]);
+    issue(k0 + 4, buf[1], eb[1], tr[1], fas[1]);
+    commit(k0 + 1, buf[2], eb[2], tr[2], fas[2]);
+    issue(k0 + 5, buf[2], eb[2], tr[2], fas[2]);
     lds_barrier();
-    // Step k commits plane k + 2 and issues plane k + 2 + PD.  The commit is
-    // unconditional (past k1 it fills a slot no later step reads), so every
-    // path through the loop consumes the same loads in the same order.
-    auto lstep = [&](int k, T (&b)[NL]) {
-      commit(k + 2, b);
-      issue(k + 2 + PD, b);
+    // Step k commits plane k + 2 and issues plane k + 2 + PD.
+    auto lstep = [&](int k, int set) {
+      commit(k + 2, buf[set], eb[set], tr[set], fas[set]);
+      issue(k + 2 + PD, buf[set], eb[set], tr[set], fas[set]);
       lds_barrier();
     };
     // whole rounds of PD steps, without exits in between (the compute waves
     // meet the extra barriers of the last round idle)
     for (int k = k0; k < k1; k += PD) {
-      lstep(k, buf[3]);
-      lstep(k + 1, buf[0]);
-      lstep(k + 2, buf[1]);
-      lstep(k + 3, buf[2]);
+      lstep(k, 3);
+      lstep(k + 1, 0);
+      lstep(k + 2, 1);
+      lstep(k + 3, 2);
     }
     return;
   }
@@ -201,116 +239,121 @@ __global__ __launch_bounds__(kBandThreads) void k_band(BandArgs a) {
   const T w0 = wc[0], w1 = wc[1], w2 = wc[2], w3 = wc[3], w4 = wc[4], w5 = wc[5],
           w6 = wc[6], w7 = wc[7], w8 = wc[8], w9 = wc[9], w10 = wc[10],
           w11 = wc[11], w12 = wc[12], w13 = wc[13], w14 = wc[14];
+  struct Two { T a, b; };  // the values at columns A and A + 1 of one row
+  auto rd2 = [&](int e) { return Two{ring[e], ring[e + 1]}; };
+  // One output row at columns A (a) and A + 1 (b) from its seven neighbour
+  // rows (dj, dk).  Interior weights are the same on every lane, and a lane
+  // shift is linear: the i + 1 terms of b (offsets 1, 8, 10, 13) are formed
+  // at the next lane's a column and the i - 1 terms of a (offsets 2, 7, 9,
+  // 14) at the previous lane's b column, each shifted once.
+  auto row_interior = [&](const Two& xc, const Two& xjp, const Two& xjm, const Two& xkp,
+                          const Two& xjmkp, const Two& xkm, const Two& xjpkm, T& oa, T& ob) {
+    const T ta = fma(w13, xjmkp.a, fma(w10, xkm.a, fma(w8, xjm.a, w1 * xc.a)));
+    const T tb = fma(w14, xjpkm.b, fma(w9, xkp.b, fma(w7, xjp.b, w2 * xc.b)));
+    T sa = fma(w13, xjmkp.b, fma(w10, xkm.b, fma(w8, xjm.b, w1 * xc.b)));
+    T sb = fma(w14, xjpkm.a, fma(w9, xkp.a, fma(w7, xjp.a, w2 * xc.a)));
+    sa = fma(w0, xc.a, sa);     sb = fma(w0, xc.b, sb);
+    sa = fma(w3, xjp.a, sa);    sb = fma(w3, xjp.b, sb);
+    sa = fma(w4, xjm.a, sa);    sb = fma(w4, xjm.b, sb);
+    sa = fma(w5, xkp.a, sa);    sb = fma(w5, xkp.b, sb);
+    sa = fma(w6, xkm.a, sa);    sb = fma(w6, xkm.b, sb);
+    sa = fma(w11, xjmkp.a, sa); sb = fma(w11, xjmkp.b, sb);
+    sa = fma(w12, xjpkm.a, sa); sb = fma(w12, xjpkm.b, sb);
+    oa = sa + lane_prev(tb);
+    ob = sb + lane_next(ta);
+  };
+  // The same with per-lane class stencils W (faces j = 0 and k = 0).
+  auto row_special = [&](const T* W, const Two& xc, const Two& xjp, const Two& xjm,
+                         const Two& xkp, const Two& xjmkp, const Two& xkm, const Two& xjpkm,
+                         T& oa, T& ob) {
+    T a = W[0] * xc.a, b = W[0] * xc.b;
+    a = fma(W[1], xc.b, a);                 b = fma(W[1], lane_next(xc.a), b);
+    a = fma(W[2], lane_prev(xc.b), a);      b = fma(W[2], xc.a, b);
+    a = fma(W[3], xjp.a, a);                b = fma(W[3], xjp.b, b);
+    a = fma(W[4], xjm.a, a);                b = fma(W[4], xjm.b, b);
+    a = fma(W[5], xkp.a, a);                b = fma(W[5], xkp.b, b);
+    a = fma(W[6], xkm.a, a);                b = fma(W[6], xkm.b, b);
+    a = fma(W[7], lane_prev(xjp.b), a);     b = fma(W[7], xjp.a, b);
+    a = fma(W[8], xjm.b, a);                b = fma(W[8], lane_next(xjm.a), b);
+    a = fma(W[9], lane_prev(xkp.b), a);     b = fma(W[9], xkp.a, b);
+    a = fma(W[10], xkm.b, a);               b = fma(W[10], lane_next(xkm.a), b);
+    a = fma(W[11], xjmkp.a, a);             b = fma(W[11], xjmkp.b, b);
+    a = fma(W[12], xjpkm.a, a);             b = fma(W[12], xjpkm.b, b);
+    a = fma(W[13], xjmkp.b, a);             b = fma(W[13], lane_next(xjmkp.a), b);
+    a = fma(W[14], lane_prev(xjpkm.b), a);  b = fma(W[14], xjpkm.a, b);
+    oa = a;
+    ob = b;
+  };
   auto compute = [&](int k) {
     const int L0 = n - jm - k + 1;
     const int rmax = R < L0 - 1 ? R : L0 - 1;  // output rows 1 .. rmax
     if (rmax < 1) return;
-    const int Ub = bstart(1, L0), Ue = bstart(rmax + 1, L0);
+    // Output rows are taken in pairs (2p + 1, 2p + 2).  The lanes run over
+    // the concatenation of the pairs' first rows (each with its pad
+    // columns): pair p starts there at E(p) = p b - p^2, b = L0 + 2.
+    const int b = L0 + 2;
+    const int npair = (rmax + 1) >> 1;
+    const int Etot = __mul24(npair, b - npair);
     const int sk = slot(k), skp = slot(k + 1), skm = slot(k - 1);
     // main-block element of image position U in output row r: Kc + U - 4 r
     const int Kc = tet32(n - 1) - tet32(n - 1 - k) - 1 + j0 * (n - 1 - k) -
-                   ((j0 * (j0 - 1)) >> 1) - Ub + 3;
-    // Two consecutive image positions per lane, A = P + 2 lane and B = A + 1:
-    // a wave covers 128 positions, of which lanes 1 .. 62 output 124.  B is
-    // A's i + 1 neighbour in the same row (unless A is the row's last pad
-    // column, whose pair is not output), so the i +- 1 terms need one lane
-    // shift per point pair instead of two per point, and each row's two
-    // values come from one paired LDS read.
-    // The pair grid starts at G = Ub or Ub - 1 so that A always maps to an
-    // even main-block element: a pair inside a row is then one aligned
-    // two-value store, and a wave's stores cover whole cache lines.
-    const int G = Ub - ((Kc + Ub) & 1);
-    const int nch = (Ue - G + 123) / 124;
-    // One chunk: the 124 outputs of lanes 1 .. 62.  SPECIAL chunks may hold
-    // points of the faces j = 0 (row 1 of the band j0 = 0) or k = 0 and take
-    // per-lane class stencils; the others take the cell's interior stencil.
+                   ((j0 * (j0 - 1)) >> 1) - bstart(1, L0) + 3;
+    const int nch = (Etot + 123) / 124;
+    // One chunk: lanes 1 .. 62 output columns A, A + 1 of the rows r and
+    // r + 1 (up to 248 points).  SPECIAL chunks may hold points of the faces
+    // j = 0 (row 1 of the band j0 = 0) or k = 0 and take per-lane class
+    // stencils; the others take the cell's interior stencil.
     auto chunk = [&](int ch, auto special) {
       constexpr bool SPECIAL = decltype(special)::value;
-      const int P = G + 124 * ch - 2;
-      const int Ar = P + 2 * lane;
-      const int A = Ar < Ub ? Ub : (Ar > Ue - 1 ? Ue - 1 : Ar);
-      int Dr;
-      const int r = brow(A, L0, Dr);
-      const int c = A - Dr, Lr = L0 - r, v = Lr + 2;
-      // the seven rows (dj, dk) at the columns of A and B
-      const int e0 = sk + A, e1 = sk + A + v, e2 = sk + A - v - 1;
-      const int e3 = skp + A - r, e4 = skp + A - r - v;
-      const int e5 = skm + A + r, e6 = skm + A + r + v + 1;
-      const T xcA = ring[e0], xcB = ring[e0 + 1];          // ( 0,  0)
-      const T xjpA = ring[e1], xjpB = ring[e1 + 1];        // (+1,  0)
-      const T xjmA = ring[e2], xjmB = ring[e2 + 1];        // (-1,  0)
-      const T xkpA = ring[e3], xkpB = ring[e3 + 1];        // ( 0, +1)
-      const T xjmkpA = ring[e4], xjmkpB = ring[e4 + 1];    // (-1, +1)
-      const T xkmA = ring[e5], xkmB = ring[e5 + 1];        // ( 0, -1)
-      const T xjpkmA = ring[e6], xjpkmB = ring[e6 + 1];    // (+1, -1)
-      T accA, accB;
+      const int ur = 124 * ch - 2 + 2 * lane;
+      const int u = ur < 0 ? 0 : (ur > Etot - 1 ? Etot - 1 : ur);
+      int Ep;
+      const int p = bpair(u, b, Ep);
+      const int r = 2 * p + 1, c = u - Ep;
+      const int A = bstart(r, L0) + c;
+      const int v = L0 - r + 2;  // positions of image row r
+      // ten rows (dj, dk) at columns A, A + 1: plane k rows r - 1 .. r + 2,
+      // plane k + 1 rows r - 1 .. r + 1, plane k - 1 rows r .. r + 2
+      const int q0 = sk + A, q1 = q0 + v, q2 = q1 + v - 1, qm = q0 - v - 1;
+      const int p0 = skp + A - r, p1 = p0 + v - 1, pm = p0 - v;
+      const int m0 = skm + A + r, m1 = m0 + v + 1, m2 = m1 + v;
+      const Two K0 = rd2(q0), K1 = rd2(q1), K2 = rd2(q2), Km = rd2(qm);
+      const Two P0 = rd2(p0), P1 = rd2(p1), Pm = rd2(pm);
+      const Two M0 = rd2(m0), M1 = rd2(m1), M2 = rd2(m2);
+      T a1, b1, a2, b2;
       if (!SPECIAL) {
-        // Interior weights are the same on every lane, and a lane shift is
-        // linear: the i + 1 terms of B (offsets 1, 8, 10, 13) are formed at
-        // A's column of the next lane and the i - 1 terms of A (offsets 2,
-        // 7, 9, 14) at B's column of the previous lane, each shifted once.
-        const T tA = fma(w13, xjmkpA, fma(w10, xkmA, fma(w8, xjmA, w1 * xcA)));
-        const T tB = fma(w14, xjpkmB, fma(w9, xkpB, fma(w7, xjpB, w2 * xcB)));
-        accA = fma(w13, xjmkpB, fma(w10, xkmB, fma(w8, xjmB, w1 * xcB)));
-        accB = fma(w14, xjpkmA, fma(w9, xkpA, fma(w7, xjpA, w2 * xcA)));
-        accA = fma(w0, xcA, accA); accB = fma(w0, xcB, accB);
-        accA = fma(w3, xjpA, accA); accB = fma(w3, xjpB, accB);
-        accA = fma(w4, xjmA, accA); accB = fma(w4, xjmB, accB);
-        accA = fma(w5, xkpA, accA); accB = fma(w5, xkpB, accB);
-        accA = fma(w6, xkmA, accA); accB = fma(w6, xkmB, accB);
-        accA = fma(w11, xjmkpA, accA); accB = fma(w11, xjmkpB, accB);
-        accA = fma(w12, xjpkmA, accA); accB = fma(w12, xjpkmB, accB);
-        accA += lane_prev(tB);
-        accB += lane_next(tA);
+        row_interior(K0, K1, Km, P0, Pm, M0, M1, a1, b1);
+        row_interior(K1, K2, K0, P1, P0, M1, M2, a2, b2);
       } else {
-        const int cls = ((jm + r == 0) << 1) | ((k == 0) << 2);
-        const T* W = wtab + cls * 15;
-        T a = W[0] * xcA, b = W[0] * xcB;
-        a = fma(W[1], xcB, a);              b = fma(W[1], lane_next(xcA), b);
-        a = fma(W[2], lane_prev(xcB), a);   b = fma(W[2], xcA, b);
-        a = fma(W[3], xjpA, a);             b = fma(W[3], xjpB, b);
-        a = fma(W[4], xjmA, a);             b = fma(W[4], xjmB, b);
-        a = fma(W[5], xkpA, a);             b = fma(W[5], xkpB, b);
-        a = fma(W[6], xkmA, a);             b = fma(W[6], xkmB, b);
-        a = fma(W[7], lane_prev(xjpB), a);  b = fma(W[7], xjpA, b);
-        a = fma(W[8], xjmB, a);             b = fma(W[8], lane_next(xjmA), b);
-        a = fma(W[9], lane_prev(xkpB), a);  b = fma(W[9], xkpA, b);
-        a = fma(W[10], xkmB, a);            b = fma(W[10], lane_next(xkmA), b);
-        a = fma(W[11], xjmkpA, a);          b = fma(W[11], xjmkpB, b);
-        a = fma(W[12], xjpkmA, a);          b = fma(W[12], xjpkmB, b);
-        a = fma(W[13], xjmkpB, a);          b = fma(W[13], lane_next(xjmkpA), b);
-        a = fma(W[14], lane_prev(xjpkmB), a); b = fma(W[14], xjpkmA, b);
-        accA = a;
-        accB = b;
+        const int kb = (k == 0) << 2;
+        row_special(wtab + 15 * (((jm + r == 0) << 1) | kb), K0, K1, Km, P0, Pm, M0, M1, a1, b1);
+        row_special(wtab + 15 * kb, K1, K2, K0, P1, P0, M1, M2, a2, b2);
       }
-      // main-block points only (2 <= c <= Lr - 1); the row ends are the
-      // face points computed below
-      const bool out = lane >= 1 && lane <= 62 && Ar == A;
-      const bool stA = out && c >= 2 && c <= Lr - 1;
-      const bool stB = out && A + 1 <= Ue - 1 && c + 1 >= 2 && c + 1 <= Lr - 1;
-      const unsigned el = (unsigned)(Kc + A - 4 * r) * (unsigned)sizeof(T);
-      // no branches: the chunk stays one basic block, which lets the
-      // scheduler overlap two chunks
-      bstore2(accA, accB, ry, stA && stB ? el : HT_OOB);
-      bstore(accA, ry, stA && !stB ? el : HT_OOB);
-      bstore(accB, ry, stB && !stA ? el + (unsigned)sizeof(T) : HT_OOB);
+      // main-block points only (2 <= c <= L_r - 1); the row ends are the
+      // face points computed below.  Row r + 1 is one point shorter.
+      const bool out = lane >= 1 && lane <= 62 && ur == u;
+      const bool two = out && r + 1 <= rmax;
+      const int Lr = L0 - r;
+      const unsigned sz = (unsigned)sizeof(T);
+      const unsigned e1 = (unsigned)(Kc + A - 4 * r) * sz;
+      const unsigned e2 = e1 + (unsigned)(v - 4) * sz;
+      // no branches: the chunk stays one basic block
+      bstore(a1, ry, out && c >= 2 && c <= Lr - 1 ? e1 : HT_OOB);
+      bstore(b1, ry, out && c >= 1 && c <= Lr - 2 ? e1 + sz : HT_OOB);
+      bstore(a2, ry, two && c >= 2 && c <= Lr - 2 ? e2 : HT_OOB);
+      bstore(b2, ry, two && c >= 1 && c <= Lr - 3 ? e2 + sz : HT_OOB);
     };
-    // chunks before nspec may touch row 1 of the band j0 = 0 (positions
-    // below D(2) = Ub + L0 + 1); on the plane k = 0 every chunk is special
-    const int nspec = k == 0 ? nch
-                      : (j0 == 0 ? min(nch, (Ub + L0 + 3 - G + 123) / 124) : 0);
+    // chunks before nspec may touch row 1 of the band j0 = 0 (pair 0, whose
+    // first row ends below E(1) = b - 1); on the plane k = 0 every chunk is
+    // special
+    const int nspec = k == 0 ? nch : (j0 == 0 ? min(nch, (b - 1 + 123) / 124) : 0);
     int ch = wave;
     for (; ch < nspec; ch += kBandComputeWaves) chunk(ch, std::true_type{});
-    // two independent chunks per iteration, so that the LDS reads of one
-    // overlap the arithmetic of the other
-    for (; ch + kBandComputeWaves < nch; ch += 2 * kBandComputeWaves) {
-      chunk(ch, std::false_type{});
-      chunk(ch + kBandComputeWaves, std::false_type{});
-    }
-    if (ch < nch) chunk(ch, std::false_type{});
+    for (; ch < nch; ch += kBandComputeWaves) chunk(ch, std::false_type{});
     // Row ends (faces i = 0 and i + j + k = n) of the output rows: lane q < R
-    // takes the first point of row q + 1, lane R + q its last point.
-    if (wave == (k & (kBandComputeWaves - 1))) {
+    // takes the first point of row q + 1, lane R + q its last point.  The
+    // wave with the fewest chunks of this plane does it.
+    if (wave == (nch & (kBandComputeWaves - 1))) {
       const bool s1 = lane >= R;
       const int r0 = (s1 ? lane - R : lane) + 1;
       const bool ok = lane < 2 * R && r0 <= rmax && (!s1 || L0 - r0 >= 2);

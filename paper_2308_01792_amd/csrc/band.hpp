@@ -18,6 +18,8 @@
 #include <hip/hip_runtime_api.h>
 #include <hip/hip_vector_types.h>
 
+#include "index.hpp"
+
 namespace ht {
 
 // LDS image capacity (values per plane slot) and ring depth.
@@ -26,16 +28,22 @@ namespace ht {
 #ifndef HT_BAND_WAVES
 #define HT_BAND_WAVES 4
 #endif
+// kBandPad values follow the ring: lanes that output nothing may read up to
+// 198 positions past a slot (at 256 intervals, the largest level whose bands
+// fit; 2048-value slots), and their values are never used.
 enum { kBandComputeWaves = HT_BAND_WAVES, kBandLoadLanes = 64 * HT_BAND_WAVES,
        kBandThreads = 128 * HT_BAND_WAVES, kBandSlots = 4, kBandDepth = 4,
-       kBandRowsMax = 32 };
+       kBandRowsMax = 32, kBandPad = 256 };
 // Values per slot (a multiple of kBandLoadLanes): four FP64 slots are 64 KB
-// and leave room for two workgroups per CU.
+// and leave room for two workgroups per CU.  FP32 uses the same count: its
+// load lanes then hold two 16-byte vectors per plane, which keeps the
+// kernel within the registers of three workgroups per CU (a larger FP32 slot
+// needs a third vector per lane and measured slower at two workgroups).
 #ifndef HT_BAND_CAP64
 #define HT_BAND_CAP64 2048
 #endif
 #ifndef HT_BAND_CAP32
-#define HT_BAND_CAP32 3072
+#define HT_BAND_CAP32 2048
 #endif
 template <typename T> struct BandCap;
 template <> struct BandCap<double> { static constexpr int value = HT_BAND_CAP64; };
@@ -84,11 +92,88 @@ inline bool make_band_items(int n, int cap, int min_rows, std::vector<int2>& ite
   return true;
 }
 
+// Geometry of plane q of the band (j0 = jm + 1, R rows, march ending at
+// k1), shared by the kernel and the host tables.  The main points of image
+// row r start at run position Mr(r) = r (L0 - 2) - r (r - 1) / 2 + 2
+// relative to element mq of the cell block (image position U of row r holds
+// element mq + U - 4 r); rows rlo .. rm - 1 have main points, which form
+// the run [F0, F1).  fa is F0 rounded down so that element mq + fa starts a
+// 16-byte vector of V values.
+struct BandPlane {
+  int L0, rows, F0, F1, fa, mq, s0b, s1b;
+  bool valid, zero;  // plane inside the cell and the march; plane outside the cell
+};
+HT_HD BandPlane band_plane(int n, int off_s0, int off_s1, int jm, int R, int k1, int q,
+                           int V) {
+  BandPlane P;
+  P.L0 = n - jm - q + 1;
+  P.valid = q >= 0 && q <= n && q <= k1 && P.L0 >= 0;
+  P.zero = (q < 0 || q > n) && q <= k1;
+  P.rows = P.valid ? (R + 2 < P.L0 + 1 ? R + 2 : P.L0 + 1) : 0;
+  const int rlo = jm < 0 ? 1 : 0;
+  const int rm = P.rows < P.L0 - 2 ? P.rows : P.L0 - 2;
+  const int L0 = P.L0;
+  auto Mr = [L0](int r) { return r * (L0 - 2) - ((r * (r - 1)) >> 1) + 2; };
+  P.F0 = Mr(rlo);
+  P.F1 = rm > rlo ? Mr(rm) : P.F0;
+  // 32-bit tetrahedral and triangular numbers (n <= 2^10 wherever bands fit)
+  auto tet = [](int w) { return w <= 0 ? 0 : w * (w + 1) * (w + 2) / 6; };
+  auto tri = [](int w) { return w <= 0 ? 0 : (w * (w + 1)) >> 1; };
+  P.mq = P.valid ? tet(n - 1) - tet(n - 1 - q) - 2 + jm * (n - 1 - q) - ((jm * (jm - 1)) >> 1)
+                 : 0;
+  P.fa = P.F0 - ((P.mq + P.F0) & (V - 1));
+  P.s0b = off_s0 + tri(n + 1) - tri(n + 1 - q) + jm;
+  P.s1b = off_s1 + tri(n) - tri(n - q) + jm;
+  return P;
+}
+
+// Main-run vectors per load lane and plane (V values each), and the bytes of
+// row data per load lane and plane (NM V, rounded up to 8 or 16).
+inline constexpr int band_nm(int cap, int V) {
+  return (cap - 4 + V - 1 + kBandLoadLanes * V - 1) / (kBandLoadLanes * V);
+}
+inline constexpr int band_tb(int nv) { return nv <= 8 ? 8 : 16; }
+// Planes per item in the row table: the march's planes k0 - 1 .. k0 + kBandPlanes.
+enum { kBandTabPlanes = kBandPlanes + 2 };
+
+// Row table.  Every cell of a level has the same closure layout, so the
+// image row of each main-run element of each plane of each work item is a
+// property of the level alone.  Byte m V + t of load lane l's TB-byte entry
+// in block 1 + item kBandTabPlanes + (q - k0 + 1) is 4 r for the run element
+// fa + V (l + kBandLoadLanes m) + t of plane q (r its image row, so that the
+// element goes to image position f + 4 r), or 0xff where that element is
+// outside [F0, F1).  Block 0 is all 0xff (planes past the march).
+inline void make_band_rowtab(int level, int cap, int esize, const std::vector<int2>& items,
+                             std::vector<uint8_t>& tab) {
+  const CellLayout L = make_layout(level);
+  const int n = L.n, V = 16 / esize, NM = band_nm(cap, V), TB = band_tb(NM * V);
+  const size_t blk = (size_t)kBandLoadLanes * TB;
+  tab.assign((1 + items.size() * (size_t)kBandTabPlanes) * blk, 0xff);
+  for (size_t it = 0; it < items.size(); ++it) {
+    const int j0 = items[it].x & 0xffff, R = items[it].x >> 16, k1 = items[it].y >> 16;
+    const int k0 = items[it].y & 0xffff, jm = j0 - 1;
+    for (int qr = 0; qr < kBandTabPlanes; ++qr) {
+      const BandPlane P = band_plane(n, (int)L.off_s0, (int)L.off_s1, jm, R, k1, k0 - 1 + qr, V);
+      if (!P.valid || P.F1 <= P.F0) continue;
+      uint8_t* t = &tab[(1 + it * (size_t)kBandTabPlanes + qr) * blk];
+      const int rlo = jm < 0 ? 1 : 0;
+      int f = P.F0;
+      for (int r = rlo; f < P.F1; ++r)
+        for (int c = 2; c <= P.L0 - r - 1; ++c, ++f) {  // main points of row r
+          const int i = f - P.fa, v = i / V;
+          t[(size_t)(v % kBandLoadLanes) * TB + (v / kBandLoadLanes) * V + i % V] =
+              (uint8_t)(4 * r);
+        }
+    }
+  }
+}
+
 struct BandArgs {
   const void* x;     // operand
   void* y;           // output (partial rows at surface points)
   const void* w;     // level-scaled class stencils [nc][16][15]
   const int2* items; // work items of one cell
+  const uint8_t* rtab;  // row table of the level (make_band_rowtab)
   int64_t nitems, nblocks;
   int64_t stride, off_s0, off_s1;
   int n;
