@@ -142,6 +142,21 @@ def batch_leg(ht, torch):
                                                  for a, b in zip(stb, stl)),
                      "max_rel_diff_vs_loop": diff}
         del ub, ul
+    # the union mesh tuned level by level on the problems present there
+    # (apply kernel, sweep rows, arrangement, march segment), then the same
+    # batched solves again
+    torch.cuda.synchronize()
+    t0 = time.time()
+    batch.autotune()
+    torch.cuda.synchronize()
+    out["autotune_seconds"] = round(time.time() - t0, 2)
+    out["tuned_shapes"] = batch.shapes(range(3, 7))
+    for name, prec in (("mixed", ht.HT_PREC_MIXED), ("f64", ht.HT_PREC_F64)):
+        run_batch(prec)
+        ub, stb = run_batch(prec)
+        out[name]["tuned_batch_seconds"] = round(stb[0]["seconds"], 4)
+        out[name]["tuned_cycles_max"] = max(x["cycles"] for x in stb)
+        del ub
     return out
 
 

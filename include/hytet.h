@@ -365,6 +365,14 @@ int ht_solve(ht_mesh* mesh, int level, const ht_solve_opts* opts, void* u,
 int ht_batch_create(ht_mesh* const* meshes, const int* levels, int n,
                     ht_batch** out);
 int ht_batch_destroy(ht_batch* batch);
+/* The batch's union mesh (owned by the batch; valid until ht_batch_destroy),
+ * for the tuning queries and setters below. */
+int ht_batch_mesh(ht_batch* batch, ht_mesh** mesh);
+/* ht_autotune for every level of the batch's union mesh from its lowest
+ * level to the largest finest level, in FP64 and FP32, each on the
+ * problems present on that level; then drops the batch's captured graphs.
+ * cache_path as for ht_autotune.  Synchronises. */
+int ht_batch_autotune(ht_batch* batch, const char* cache_path, ht_stream stream);
 /* Number of problems, their total unknowns (interior DoFs at each problem's
  * finest level) and total macro-cells; any output may be NULL. */
 int ht_batch_query(const ht_batch* batch, int* n_problems, int64_t* n_dofs,
@@ -436,12 +444,23 @@ int ht_set_sweep_shape(ht_mesh* mesh, int level, int dtype, int rows,
                        int waves_in_i);
 int ht_get_sweep_shape(const ht_mesh* mesh, int level, int dtype, int* rows,
                        int* waves_in_i);
-/* Autotuner: times every R on the live apply at (level, dtype) on `stream`
- * and every (R, arrangement) on the live Jacobi sweep (three scratch
- * vectors are allocated and freed), keeps the fastest of each and returns the
- * apply's R in *rows.  With cache_path != NULL a text cache keyed by
- * (gfx arch, level, dtype, cells, cell stride) is read first and appended
- * to after tuning.  Synchronises. */
+/* March segment of the sweep operations: a wavefront's k-march is split
+ * into segments of `planes` planes (32, 64 or 128; each segment reloads two
+ * planes), which evens out the work per wave.  Default 32 with the waves
+ * side by side in i, 64 stacked.  HT_ERR_ARG for another length.  Results
+ * do not depend on it. */
+int ht_set_march_segment(ht_mesh* mesh, int level, int dtype, int planes);
+int ht_get_march_segment(const ht_mesh* mesh, int level, int dtype, int* planes);
+/* Autotuner: times the band kernel and every R on the live apply at
+ * (level, dtype) on `stream`, and every (R, arrangement, march segment) on
+ * the live Jacobi sweep (three scratch vectors are allocated and freed),
+ * keeps the fastest of each and returns the apply's choice in *rows (0 =
+ * band kernel).  Only the cells present on the level take part (all of a
+ * plain mesh; in a batch's union mesh, the problems whose finest level is at
+ * least `level`).  With cache_path != NULL a text cache keyed by (gfx arch,
+ * level, dtype, cells, cell stride) is read first and appended to after
+ * tuning.  Captured graphs of the mesh are dropped (they hold the old
+ * shapes).  Synchronises. */
 int ht_autotune(ht_mesh* mesh, int level, int dtype, const char* cache_path,
                 int* rows, ht_stream stream);
 

@@ -361,6 +361,15 @@ class Mesh:
                                         C.byref(r), C.byref(w)))
         return r.value, bool(w.value)
 
+    def set_march_segment(self, level: int, dtype_code: int, planes: int):
+        check(load().ht_set_march_segment(self._h, level, dtype_code, planes))
+
+    def march_segment(self, level: int, dtype_code: int) -> int:
+        """Planes per march segment of the sweep operations."""
+        r = C.c_int()
+        check(load().ht_get_march_segment(self._h, level, dtype_code, C.byref(r)))
+        return r.value
+
     def autotune(self, level: int, dtype_code: int, cache_path=None) -> int:
         r = C.c_int()
         check(load().ht_autotune(self._h, level, dtype_code,
@@ -418,6 +427,31 @@ class Batch:
         check(load().ht_batch_query(self._h, C.byref(n), C.byref(d),
                                     C.byref(c)))
         return {"problems": n.value, "dofs": d.value, "cells": c.value}
+
+    def autotune(self, cache_path=None):
+        """Tune the tile shapes of every level of the union mesh (FP64 and
+        FP32) on the problems present there."""
+        check(load().ht_batch_autotune(
+            self._h, cache_path.encode() if cache_path else None, _stream()))
+
+    def shapes(self, levels) -> dict:
+        """Tile shapes of the union mesh per level: apply rows (0 = band
+        kernel), sweep rows, sweep waves side by side in i, sweep march
+        segment, for FP64 and FP32."""
+        lib = load()
+        m = C.c_void_p()
+        check(lib.ht_batch_mesh(self._h, C.byref(m)))
+        out = {}
+        for lv in levels:
+            for name, code in (("f64", HT_F64), ("f32", HT_F32)):
+                a, r, w, g = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+                check(lib.ht_get_tile_rows(m, lv, code, C.byref(a)))
+                check(lib.ht_get_sweep_shape(m, lv, code, C.byref(r), C.byref(w)))
+                check(lib.ht_get_march_segment(m, lv, code, C.byref(g)))
+                out.setdefault(str(lv), {})[name] = {
+                    "apply_rows": a.value, "sweep_rows": r.value,
+                    "waves_in_i": bool(w.value), "segment": g.value}
+        return out
 
     def solve(self, us, bs, rel_tol=1e-10, max_cycles=100, nu1=2, nu2=2,
               omega=2.0 / 3.0, coarse_level=2, use_graph=True,

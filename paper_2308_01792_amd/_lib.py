@@ -101,6 +101,10 @@ SIGNATURES = {
     "ht_get_tile_rows": (I, [P, I, I, C.POINTER(I)]),
     "ht_set_sweep_shape": (I, [P, I, I, I, I]),
     "ht_get_sweep_shape": (I, [P, I, I, C.POINTER(I), C.POINTER(I)]),
+    "ht_set_march_segment": (I, [P, I, I, I]),
+    "ht_get_march_segment": (I, [P, I, I, C.POINTER(I)]),
+    "ht_batch_mesh": (I, [P, C.POINTER(P)]),
+    "ht_batch_autotune": (I, [P, C.c_char_p, P]),
     "ht_autotune": (I, [P, I, I, C.c_char_p, C.POINTER(I), P]),
     "ht_profile_enable": (I, [P, I]),
     "ht_profile_query": (I, [P, C.c_char_p, C.POINTER(D), C.POINTER(L)]),

@@ -41,11 +41,19 @@ struct Batch {
 };
 }  // namespace ht
 
+// Tuned tile shape of the sweep operations at one (level, dtype).
+struct SweepShape {
+  int J;
+  bool in_i;
+  int seg;
+};
+
 struct ht_mesh {
   ht::Mesh m;
   // (level, J) -> tile list on the device
   // (level, J, waves side by side in i) -> tile list on the device
-  std::map<std::tuple<int, int, bool>, std::pair<int2*, int64_t>> tiles;
+  // (level, J, waves in i, planes per march segment; 0 = unsegmented)
+  std::map<std::tuple<int, int, bool, int>, std::pair<int2*, int64_t>> tiles;
   // level -> walk tiles (64 i x 8 rows) for the transfer / elementwise kernels
   std::map<int, std::pair<int2*, int64_t>> walk_tiles;
   std::map<std::pair<int, int>, int> tuned_J;  // (level, dtype) -> J
@@ -55,7 +63,7 @@ struct ht_mesh {
   // (level, dtype) -> the band kernel's row table (make_band_rowtab)
   std::map<std::pair<int, int>, uint8_t*> band_rowtab;
   // (level, dtype) -> (J, waves side by side in i) of the sweep operations
-  std::map<std::pair<int, int>, std::pair<int, bool>> tuned_sweep;
+  std::map<std::pair<int, int>, SweepShape> tuned_sweep;
   std::map<int, double> lambda_max;            // level -> estimate
   // (fine level, J) -> P2 k-march segments; fine level -> P2 face runs
   std::map<std::pair<int, int>, std::pair<int2*, int64_t>> p2_tiles;
@@ -150,17 +158,19 @@ static const int kDefaultJ = 4;
 // measured at level 8, 64 suits the stacked arrangement, 32 the side-by-side
 // one.
 static int march_segment(bool in_i) { return in_i ? 32 : 64; }
+// segment lengths the autotuner tries for the sweeps (the shortest bounds the
+// norm partials a launch may need)
+static const int kSegs[] = {32, 64, 128};
 
-// Tiles (i0, j0) of one cell; with `segmented` (the stencil kernel) each tile
-// is split into march segments (i0, j0 | k0 << 16).
-static std::vector<int2> make_tiles(int n, int J, bool in_i, bool segmented = false) {
+// Tiles (i0, j0) of one cell; with seg > 0 (the stencil kernel) each tile is
+// split into march segments of seg planes (i0, j0 | k0 << 16).
+static std::vector<int2> make_tiles(int n, int J, bool in_i, int seg = 0) {
   std::vector<int2> t;
   const int GJ = in_i ? J : kCellWaves * J, GI = in_i ? 62 * kCellWaves : 62;
-  const int seg = march_segment(in_i);
   for (int tj = 0; GJ * tj <= n; ++tj)
     for (int ti = 0; GI * ti + GJ * tj <= n; ++ti) {
-      const int kcol = segmented ? n - GI * ti - GJ * tj : 0;
-      for (int k0 = 0; k0 <= kcol; k0 += seg) t.push_back(make_int2(GI * ti, GJ * tj | (k0 << 16)));
+      const int kcol = seg > 0 ? n - GI * ti - GJ * tj : 0;
+      for (int k0 = 0; k0 <= kcol; k0 += (seg > 0 ? seg : 1)) t.push_back(make_int2(GI * ti, GJ * tj | (k0 << 16)));
     }
   return t;
 }
@@ -178,7 +188,7 @@ static int64_t partials_needed(const ht_mesh* h, int level) {
   int64_t cell_blocks = 0;
   for (int J : kJ)
     for (bool in_i : {false, true})
-      cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J, in_i, true).size());
+      cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J, in_i, kSegs[0]).size());
   const int64_t fp = n_tri(n - 2), total = m.n_faces * fp + m.n_edges * std::max(n - 1, 0) + m.n_verts;
   const int64_t exch_blocks = (total + 255) / 256;
   const int64_t elem_blocks = m.nc * (int64_t)make_walk_tiles(n).size();
@@ -243,8 +253,8 @@ void ensure_uploaded_h(ht_mesh* h) {
     m.d_w32[l] = upload(wf);
     for (int J : kJ)
       for (bool in_i : {false, true}) {
-        auto t = make_tiles(1 << l, J, in_i, true);
-        h->tiles[{l, J, in_i}] = {upload(t), (int64_t)t.size()};
+        auto t = make_tiles(1 << l, J, in_i, march_segment(in_i));
+        h->tiles[{l, J, in_i, march_segment(in_i)}] = {upload(t), (int64_t)t.size()};
       }
     {
       auto t = make_walk_tiles(1 << l);
@@ -329,16 +339,31 @@ static int choose_J(ht_mesh* h, int level, int dtype) {
 struct Shape {
   int J;
   bool in_i;
+  int seg;  // planes per march segment
 };
 static Shape choose_shape(ht_mesh* h, int level, int dtype, int op) {
-  if (op == OP_APPLY) return Shape{choose_J(h, level, dtype), false};
+  if (op == OP_APPLY) return Shape{choose_J(h, level, dtype), false, march_segment(false)};
   if (!op_is_sweep(op)) {
     const int J = choose_J(h, level, dtype);
-    return Shape{J == 0 ? kDefaultJ : J, false};
+    return Shape{J == 0 ? kDefaultJ : J, false, march_segment(false)};
   }
   auto it = h->tuned_sweep.find({level, dtype});
-  if (it != h->tuned_sweep.end()) return Shape{it->second.first, it->second.second};
-  return Shape{kDefaultJ, (1 << level) >= 62 * (kCellWaves - 1) + 1};
+  if (it != h->tuned_sweep.end()) return Shape{it->second.J, it->second.in_i, it->second.seg};
+  const bool in_i = (1 << level) >= 62 * (kCellWaves - 1) + 1;
+  return Shape{kDefaultJ, in_i, march_segment(in_i)};
+}
+// Segmented tiles of a shape, uploaded on first use (never under graph
+// capture: the defaults exist from set-up, and the autotuner and the shape
+// setters create the others before any launch uses them).
+static const std::pair<int2*, int64_t>& seg_tiles(ht_mesh* h, int level, int J, bool in_i,
+                                                  int seg) {
+  auto it = h->tiles.find({level, J, in_i, seg});
+  if (it == h->tiles.end()) {
+    auto t = make_tiles(1 << level, J, in_i, seg);
+    it = h->tiles.emplace(std::make_tuple(level, J, in_i, seg),
+                          std::make_pair(upload(t), (int64_t)t.size())).first;
+  }
+  return it->second;
 }
 
 // Stencil-kernel arguments over the cells of R: every per-cell array is
@@ -358,9 +383,9 @@ static CellArgs cell_args(ht_mesh* h, int level, int dtype, const Shape& sh,
   a.w = (const char*)level_weights(h, level, dtype) + R.c0 * 240 * (int64_t)esize(dtype);
   a.cls = m.d_cls + 16 * R.c0;
   a.partials = m.d_partials;
-  auto& t = h->tiles.at({level, sh.J, sh.in_i});
+  auto& t = h->tiles.at({level, sh.J, sh.in_i, sh.seg});
   a.waves_in_i = sh.in_i ? 1 : 0;
-  a.kseg = march_segment(sh.in_i);
+  a.kseg = sh.seg;
   a.tiles = t.first;
   a.ntiles = t.second;
   a.nblocks = (R.c1 - R.c0) * t.second;
@@ -523,10 +548,10 @@ static const void* vcoef_couplings(ht_mesh* h, int level, int dtype) {
 // Unsegmented tiles for the variable-coefficient kernel, cached under -J so
 // that they never mix with the stencil kernel's segmented tiles.
 static const std::pair<int2*, int64_t>& tiles_of(ht_mesh* h, int level, int J) {
-  auto it = h->tiles.find({level, -J, false});
+  auto it = h->tiles.find({level, -J, false, 0});
   if (it == h->tiles.end()) {
     auto t = make_tiles(1 << level, J, false);
-    it = h->tiles.emplace(std::make_tuple(level, -J, false),
+    it = h->tiles.emplace(std::make_tuple(level, -J, false, 0),
                           std::make_pair(upload(t), (int64_t)t.size())).first;
   }
   return it->second;
@@ -1963,6 +1988,29 @@ int ht_batch_destroy(ht_batch* B) {
   });
 }
 
+static void autotune_level(ht_mesh* h, int level, int dtype, const char* cache_path,
+                           int* rows, hipStream_t s);
+static void drop_graphs(ht_mesh* h);
+
+int ht_batch_mesh(ht_batch* B, ht_mesh** mesh) {
+  return guard([&] {
+    if (!B || !mesh) throw Error{HT_ERR_ARG, "NULL argument"};
+    *mesh = B->mesh;
+  });
+}
+
+int ht_batch_autotune(ht_batch* B, const char* cache_path, ht_stream stream) {
+  return guard([&] {
+    if (!B) throw Error{HT_ERR_ARG, "batch is NULL"};
+    ht_mesh* h = B->mesh;
+    ensure_uploaded_h(h);
+    hipStream_t s = (hipStream_t)stream;
+    for (int l = h->m.min_level; l <= B->bt.lmax; ++l)
+      for (int dt : {HT_F64, HT_F32}) autotune_level(h, l, dt, cache_path, nullptr, s);
+    drop_graphs(h);
+  });
+}
+
 int ht_batch_query(const ht_batch* B, int* n_problems, int64_t* n_dofs,
                    int64_t* n_cells) {
   return guard([&] {
@@ -2166,7 +2214,10 @@ int ht_set_sweep_shape(ht_mesh* h, int level, int dtype, int rows, int waves_in_
       throw Error{HT_ERR_ARG, "tile rows must be 4, 8 or 16"};
     if (waves_in_i != 0 && waves_in_i != 1)
       throw Error{HT_ERR_ARG, "waves_in_i must be 0 or 1"};
-    h->tuned_sweep[{level, dtype}] = {rows, waves_in_i != 0};
+    auto it = h->tuned_sweep.find({level, dtype});
+    const int seg = it != h->tuned_sweep.end() ? it->second.seg : march_segment(waves_in_i != 0);
+    if (h->m.uploaded) seg_tiles(h, level, rows, waves_in_i != 0, seg);
+    h->tuned_sweep[{level, dtype}] = {rows, waves_in_i != 0, seg};
   });
 }
 
@@ -2182,54 +2233,93 @@ int ht_get_sweep_shape(const ht_mesh* h, int level, int dtype, int* rows,
   });
 }
 
-int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
-                int* rows, ht_stream stream) {
+int ht_set_march_segment(ht_mesh* h, int level, int dtype, int planes) {
   return guard([&] {
-    HT_DEV_PROLOGUE(level, dtype);
-    // cache: lines "<gfx arch> <level> <dtype> <cells> <stride> v2
-    // <apply rows> <sweep rows> <sweep waves in i>"
-    hipDeviceProp_t prop;
-    HT_CHECK_HIP(hipGetDeviceProperties(&prop, h->m.device));
-    const CellLayout L = make_layout(level);
-    std::ostringstream key;
-    key << prop.gcnArchName << ' ' << level << ' ' << dtype << ' ' << h->m.nc
-        << ' ' << L.stride << " v2";
-    auto valid_rows = [](int J) { return J == 4 || J == 8 || J == 16; };
-    auto valid_apply = [&](int J) { return valid_rows(J) || (J == 0 && has_band(h, level, dtype)); };
-    if (cache_path) {
-      FILE* f = std::fopen(cache_path, "r");
-      if (f) {
-        char line[512];
-        while (std::fgets(line, sizeof line, f)) {
-          const std::string ln(line), k = key.str() + ' ';
-          int J = 0, sJ = 0, sI = -1;
-          if (ln.compare(0, k.size(), k) == 0 &&
-              std::sscanf(ln.c_str() + k.size(), "%d %d %d", &J, &sJ, &sI) == 3 &&
-              valid_apply(J) && valid_rows(sJ) && (sI == 0 || sI == 1)) {
-            h->tuned_J[{level, dtype}] = J;
-            h->tuned_sweep[{level, dtype}] = {sJ, sI == 1};
-            if (rows) *rows = J;
-            std::fclose(f);
-            return;
-          }
+    if (!h) throw Error{HT_ERR_ARG, "mesh is NULL"};
+    check_level(h->m, level);
+    check_dtype(dtype);
+    if (std::find(std::begin(kSegs), std::end(kSegs), planes) == std::end(kSegs))
+      throw Error{HT_ERR_ARG, "march segment must be 32, 64 or 128 planes"};
+    const Shape sh = choose_shape(h, level, dtype, OP_JACOBI);
+    if (h->m.uploaded) seg_tiles(h, level, sh.J, sh.in_i, planes);
+    h->tuned_sweep[{level, dtype}] = {sh.J, sh.in_i, planes};
+  });
+}
+
+int ht_get_march_segment(const ht_mesh* h, int level, int dtype, int* planes) {
+  return guard([&] {
+    if (!h || !planes) throw Error{HT_ERR_ARG, "NULL argument"};
+    check_level(h->m, level);
+    check_dtype(dtype);
+    *planes = choose_shape(const_cast<ht_mesh*>(h), level, dtype, OP_JACOBI).seg;
+  });
+}
+
+// The cells (and their faces, edges, vertices) present on `level`: all of
+// a plain mesh, the problems whose finest level is at least `level` in the
+// union mesh of a batch (a prefix of its problems).
+static Range level_range(const Mesh& m, int level) {
+  int p1 = 0;
+  while (p1 < m.nprob && m.pcell[p1 + 1] <= m.act_cells[level]) ++p1;
+  return problem_range(m, 0, p1);
+}
+
+// Autotuning of one (level, dtype) over the cells present on the level.
+static void autotune_level(ht_mesh* h, int level, int dtype, const char* cache_path,
+                           int* rows, hipStream_t s) {
+  // cache: lines "<gfx arch> <level> <dtype> <cells> <stride> v3
+  // <apply rows> <sweep rows> <sweep waves in i> <sweep segment>"
+  hipDeviceProp_t prop;
+  HT_CHECK_HIP(hipGetDeviceProperties(&prop, h->m.device));
+  const CellLayout L = make_layout(level);
+  const Range R = level_range(h->m, level);
+  if (R.c1 <= R.c0) return;  // no cell on this level
+  std::ostringstream key;
+  key << prop.gcnArchName << ' ' << level << ' ' << dtype << ' ' << (R.c1 - R.c0) << ' '
+      << L.stride << " v3";
+  auto valid_rows = [](int J) { return J == 4 || J == 8 || J == 16; };
+  auto valid_apply = [&](int J) { return valid_rows(J) || (J == 0 && has_band(h, level, dtype)); };
+  auto valid_seg = [](int g) { return std::find(std::begin(kSegs), std::end(kSegs), g) != std::end(kSegs); };
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      while (std::fgets(line, sizeof line, f)) {
+        const std::string ln(line), k = key.str() + ' ';
+        int J = 0, sJ = 0, sI = -1, sg = 0;
+        if (ln.compare(0, k.size(), k) == 0 &&
+            std::sscanf(ln.c_str() + k.size(), "%d %d %d %d", &J, &sJ, &sI, &sg) == 4 &&
+            valid_apply(J) && valid_rows(sJ) && (sI == 0 || sI == 1) && valid_seg(sg)) {
+          seg_tiles(h, level, sJ, sI == 1, sg);
+          h->tuned_J[{level, dtype}] = J;
+          h->tuned_sweep[{level, dtype}] = {sJ, sI == 1, sg};
+          if (rows) *rows = J;
+          std::fclose(f);
+          return;
         }
-        std::fclose(f);
       }
+      std::fclose(f);
     }
-    const size_t bytes = level_slots(h->m, level) * esize(dtype);
-    void* x = dalloc<char>(bytes);
-    void* y = dalloc<char>(bytes);
-    void* bv = nullptr;
-    try {
-      bv = dalloc<char>(bytes);
-    } catch (...) {
-      (void)hipFree(x); (void)hipFree(y);
-      throw;
-    }
-    hipEvent_t e0, e1;
+  }
+  const size_t bytes = level_slots(h->m, level) * esize(dtype);
+  void* x = dalloc<char>(bytes);
+  void* y = nullptr;
+  void* bv = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool was_profiling = h->m.profiling;
+  int best = choose_J(h, level, dtype);
+  SweepShape best_sweep{kDefaultJ, true, march_segment(true)};
+  auto release = [&] {
+    h->m.profiling = was_profiling;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(x); (void)hipFree(y); (void)hipFree(bv);
+  };
+  try {
+    y = dalloc<char>(bytes);
+    bv = dalloc<char>(bytes);
     HT_CHECK_HIP(hipEventCreate(&e0));
     HT_CHECK_HIP(hipEventCreate(&e1));
-    const bool was_profiling = h->m.profiling;
     h->m.profiling = false;
     // mean time of five launches of `pass` after two untimed ones
     auto time_of = [&](const std::function<void()>& pass) {
@@ -2242,53 +2332,62 @@ int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
       HT_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
       return ms;
     };
-    int best = choose_J(h, level, dtype);
-    std::pair<int, bool> best_sweep{kDefaultJ, true};
-    try {
-      // apply: the band kernel, or the tile kernel with J rows per wave and
-      // the waves stacked in j
-      float best_ms = 1e30f;
-      std::vector<int> cand(std::begin(kJ), std::end(kJ));
-      if (has_band(h, level, dtype)) cand.insert(cand.begin(), 0);
-      for (int J : cand) {
-        h->tuned_J[{level, dtype}] = J;
-        const float ms = time_of([&] { op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s); });
-        if (ms < best_ms) { best_ms = ms; best = J; }
-      }
-      h->tuned_J[{level, dtype}] = best;
-      // sweeps: rows per wave and wave arrangement, on the Jacobi sweep
-      // with its own right-hand side (b streams from HBM as in a solve)
-      best_ms = 1e30f;
-      for (int J : kJ)
-        for (bool in_i : {false, true}) {
-          h->tuned_sweep[{level, dtype}] = {J, in_i};
-          const float ms = time_of(
-              [&] { op_pass(h, level, dtype, OP_JACOBI, x, y, bv, 2.0 / 3.0, s); });
-          if (ms < best_ms) { best_ms = ms; best_sweep = {J, in_i}; }
-        }
-    } catch (...) {
-      h->m.profiling = was_profiling;
-      h->tuned_sweep.erase({level, dtype});
-      (void)hipFree(x); (void)hipFree(y); (void)hipFree(bv);
-      throw;
+    // apply: the band kernel, or the tile kernel with J rows per wave and
+    // the waves stacked in j
+    float best_ms = 1e30f;
+    std::vector<int> cand(std::begin(kJ), std::end(kJ));
+    if (has_band(h, level, dtype)) cand.insert(cand.begin(), 0);
+    for (int J : cand) {
+      h->tuned_J[{level, dtype}] = J;
+      const float ms = time_of([&] { op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s, false, 0, R); });
+      if (ms < best_ms) { best_ms = ms; best = J; }
     }
-    h->m.profiling = was_profiling;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(x);
-    (void)hipFree(y);
-    (void)hipFree(bv);
     h->tuned_J[{level, dtype}] = best;
-    h->tuned_sweep[{level, dtype}] = best_sweep;
-    if (rows) *rows = best;
-    if (cache_path) {
-      FILE* f = std::fopen(cache_path, "a");
-      if (f) {
-        std::fprintf(f, "%s %d %d %d\n", key.str().c_str(), best, best_sweep.first,
-                     best_sweep.second ? 1 : 0);
-        std::fclose(f);
-      }
+    // sweeps: rows per wave, wave arrangement and march segment length, on
+    // the Jacobi sweep with its own right-hand side (b streams from HBM as
+    // in a solve)
+    best_ms = 1e30f;
+    for (int J : kJ)
+      for (bool in_i : {false, true})
+        for (int sg : kSegs) {
+          seg_tiles(h, level, J, in_i, sg);
+          h->tuned_sweep[{level, dtype}] = {J, in_i, sg};
+          const float ms = time_of(
+              [&] { op_pass(h, level, dtype, OP_JACOBI, x, y, bv, 2.0 / 3.0, s, false, 0, R); });
+          if (ms < best_ms) { best_ms = ms; best_sweep = {J, in_i, sg}; }
+        }
+  } catch (...) {
+    h->tuned_sweep.erase({level, dtype});
+    release();
+    throw;
+  }
+  release();
+  h->tuned_J[{level, dtype}] = best;
+  h->tuned_sweep[{level, dtype}] = best_sweep;
+  if (rows) *rows = best;
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s %d %d %d %d\n", key.str().c_str(), best, best_sweep.J,
+                   best_sweep.in_i ? 1 : 0, best_sweep.seg);
+      std::fclose(f);
     }
+  }
+}
+
+// captured graphs hold the launch shapes of their capture
+static void drop_graphs(ht_mesh* h) {
+  if (h->m.uploaded) (void)hipDeviceSynchronize();
+  for (auto& kv : h->m.graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  h->m.graphs.clear();
+}
+
+int ht_autotune(ht_mesh* h, int level, int dtype, const char* cache_path,
+                int* rows, ht_stream stream) {
+  return guard([&] {
+    HT_DEV_PROLOGUE(level, dtype);
+    autotune_level(h, level, dtype, cache_path, rows, s);
+    drop_graphs(h);
   });
 }
 

@@ -175,3 +175,27 @@ def test_coarse_level_above_a_problem_is_rejected(setup):
     us = [torch.zeros_like(b) for b in bs]
     with pytest.raises(ht.HytetError, match="HT_ERR_LEVEL"):
         batch.solve(us, bs, coarse_level=4)
+
+
+def test_autotuned_batch_matches_individual_solves():
+    """The batch's union mesh tuned level by level on the problems present
+    there (apply kernel, sweep rows, arrangement and march segment) solves
+    to the same iterates and cycle counts as the untuned loop of single
+    solves, in FP64 and FP32-in-FP64."""
+    meshes = [ht.Mesh(p.xyz, p.cells, 2, p.level) for p in PROBLEMS]
+    bs = [_rhs(m, p.level, 100 + p.index) for m, p in zip(meshes, PROBLEMS)]
+    batch = ht.Batch(meshes, [p.level for p in PROBLEMS])
+    batch.autotune()
+    shapes = batch.shapes(range(3, 6))
+    for lv, per in shapes.items():
+        for name, sh in per.items():
+            assert sh["apply_rows"] in (0, 4, 8, 16)
+            assert sh["sweep_rows"] in (4, 8, 16)
+            assert sh["segment"] in (32, 64, 128)
+    for prec in (ht.HT_PREC_F64, ht.HT_PREC_MIXED):
+        us = [torch.zeros_like(b) for b in bs]
+        st = batch.solve(us, bs, rel_tol=1e-10, max_cycles=100, precision=prec)
+        ref = _individual(meshes, bs, prec, rel_tol=1e-10, max_cycles=100)
+        for (ur, sr), u, s in zip(ref, us, st):
+            assert s["cycles"] == sr["cycles"]
+            assert rel_err(u.cpu().numpy(), ur.cpu().numpy()) <= 1e-12

@@ -13,6 +13,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_2308_01792_amd as ht  # noqa: E402
+from tests.conftest import mesh_by_name  # noqa: E402
 from tests.gpu_support import Pair, rel_err  # noqa: E402
 from workloads import fields  # noqa: E402
 
@@ -382,9 +383,48 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     P.m.set_tile_rows(4, ht.HT_F64, 4 if rows != 4 else 8)
     P.m.set_sweep_shape(4, ht.HT_F64, 16 if sweep[0] != 16 else 8,
                         not sweep[1])
+    seg = P.m.march_segment(4, ht.HT_F64)
+    assert seg in (32, 64, 128)
+    P.m.set_march_segment(4, ht.HT_F64, 128 if seg != 128 else 32)
     assert P.m.autotune(4, ht.HT_F64, cache) == rows      # from the cache
     assert P.m.sweep_shape(4, ht.HT_F64) == sweep
+    assert P.m.march_segment(4, ht.HT_F64) == seg
     assert open(cache).read().count("\n") == 1
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_sweeps_do_not_depend_on_the_march_segment(dt):
+    """Jacobi sweeps and the residual with every march segment length give
+    the same values (a segment only changes which wave computes a plane);
+    the residual norm may differ in rounding (its partial sums are grouped by
+    wave)."""
+    L = 6   # columns of up to 65 planes: one, two or three segments
+    m = ht.Mesh(*mesh_by_name("jittered_288"), 2, L)
+    code = ht.HT_F64 if dt == torch.float64 else ht.HT_F32
+    rng = np.random.default_rng(8)
+    n = m.n_slots(L)
+    u0 = torch.tensor(rng.uniform(-1, 1, n), dtype=dt, device="cuda")
+    b = torch.tensor(rng.uniform(-1, 1, n), dtype=dt, device="cuda")
+    m.sync(L, u0)
+    m.sync(L, b)
+    outs = []
+    for in_i in (False, True):
+        m.set_sweep_shape(L, code, 4, in_i)
+        for seg in (32, 64, 128):
+            m.set_march_segment(L, code, seg)
+            assert m.march_segment(L, code) == seg
+            assert m.sweep_shape(L, code) == (4, in_i)
+            u = u0.clone()
+            m.smooth_jacobi(L, u, b, sweeps=3)
+            r = torch.zeros_like(u)
+            nr = m.residual(L, u, b, r, want_norm=True)
+            outs.append((u, r, nr))
+    for u, r, nr in outs[1:]:
+        assert torch.equal(u, outs[0][0]) and torch.equal(r, outs[0][1])
+        assert abs(nr - outs[0][2]) <= 1e-12 * outs[0][2]
+    with pytest.raises(ht.HytetError):
+        m.set_march_segment(L, code, 48)
+    m.close()
 
 
 @pytest.mark.parametrize("cycles", [1, 3])

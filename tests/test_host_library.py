@@ -104,6 +104,17 @@ def test_mesh_errors(lib):
     with pytest.raises(ht.HytetError) as e:
         m.set_tile_rows(3, _lib.HT_F64, 5)
     assert e.value.code == _lib.HT_ERR_ARG
+    # march segments of the sweeps: 32 side by side in i, 64 stacked by
+    # default; 32, 64 or 128 accepted
+    m.set_sweep_shape(3, _lib.HT_F32, 8, False)
+    assert m.march_segment(3, _lib.HT_F32) == 64
+    m.set_march_segment(3, _lib.HT_F32, 128)
+    assert m.march_segment(3, _lib.HT_F32) == 128
+    assert m.sweep_shape(3, _lib.HT_F32) == (8, False)
+    for bad in (0, 16, 48, 256):
+        with pytest.raises(ht.HytetError) as e:
+            m.set_march_segment(3, _lib.HT_F32, bad)
+        assert e.value.code == _lib.HT_ERR_ARG
 
 
 def _slot_local_index(m, level, keys, flags):
