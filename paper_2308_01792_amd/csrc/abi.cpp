@@ -639,17 +639,30 @@ static std::vector<int2> make_p2_columns(int n, int J, int seg) {
     }
   return t;
 }
-// Face runs of one cell: (k | side << 16 | s << 17, j0) for the points
-// j = j0 + 2 lane + s of plane k on face i = 0 (side 0, j + k <= n) or on
-// the slanted face (side 1, j + k <= n - 1).
+// Face runs of one cell, for the points of face i = 0 (side 0, j + k <= n)
+// and of the slanted face (side 1, j + k <= n - 1), 64 points of one node
+// parity per run:
+//   interior runs (k | side << 16 | s << 17, j0): the points
+//     j = 1 + j0 + 2 lane + s of plane k with 1 <= j <= n - k - 1, which
+//     share one boundary class;
+//   edge runs (side << 16 | s << 17 | 1 << 18 | edge << 19, k0): the points
+//     k = k0 + 2 lane + s of the edge j = 0 (edge 0) or, on face i = 0, of
+//     the edge j = n - k with k < n (edge 1), each with its own class.
 static std::vector<int2> make_p2_runs(int n) {
   std::vector<int2> t;
   for (int k = 0; k <= n; ++k)
     for (int side = 0; side < 2; ++side) {
-      const int jmax = side == 0 ? n - k : n - k - 1;
-      for (int j0 = 0; j0 <= jmax; j0 += 128)
-        for (int s = 0; s < 2 && j0 + s <= jmax; ++s)
+      const int jmax = n - k - 1;  // interior rows: 1 <= j <= n - k - 1
+      for (int j0 = 0; 1 + j0 <= jmax; j0 += 128)
+        for (int s = 0; s < 2 && 1 + j0 + s <= jmax; ++s)
           t.push_back(make_int2(k | (side << 16) | (s << 17), j0));
+    }
+  for (int side = 0; side < 2; ++side)
+    for (int edge = 0; edge < (side == 0 ? 2 : 1); ++edge) {
+      const int kmax = side == 0 ? (edge ? n - 1 : n) : n - 1;
+      for (int k0 = 0; k0 <= kmax; k0 += 128)
+        for (int s = 0; s < 2 && k0 + s <= kmax; ++s)
+          t.push_back(make_int2((side << 16) | (s << 17) | (1 << 18) | (edge << 19), k0));
     }
   return t;
 }

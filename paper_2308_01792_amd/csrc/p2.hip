@@ -167,17 +167,20 @@ __global__ __launch_bounds__(256) void k_p2_march(P2Args a) {
 // stencil is unrolled at compile time; entries that always have zero weight
 // on that face (di < 0 on i = 0, di + dj + dk > 0 on the slanted face) are
 // dropped, so every remaining neighbour lies inside the closure whenever its
-// row exists.
-template <typename T, int P, int SIDE>
+// row exists.  UNIFORM: every valid lane has the boundary class of lane 0
+// (the interior rows of a face), so the stencil weights are read once per
+// wave (scalar loads) instead of once per lane.
+template <typename T, int P, int SIDE, bool UNIFORM>
 __device__ __forceinline__ void p2_face_points(const P2Args& a, int64_t cell,
-                                               int k, int j) {
+                                               int k, int j, bool valid) {
   const int n = a.n;
-  const bool valid = SIDE == 0 ? j + k <= n : j + k <= n - 1;
   const int i = SIDE == 0 ? 0 : n - j - k;
   const int64_t bytes = a.stride * (int64_t)sizeof(T);
   const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
+  const int cls = UNIFORM ? __builtin_amdgcn_readfirstlane(point_class(n, i, j, k))
+                          : point_class(n, i, j, k);
   const T* wp = (const T*)a.w + cell * (int64_t)kP2PerCell +
-                (P * kNumClasses + point_class(n, i, j, k)) * kP2MaxOffsets;
+                (P * kNumClasses + cls) * kP2MaxOffsets;
   T acc = 0;
   static_for<kP2Off.len[P]>([&](auto TT) {
     constexpr int t = decltype(TT)::value;
@@ -185,14 +188,16 @@ __device__ __forceinline__ void p2_face_points(const P2Args& a, int64_t cell,
     if constexpr ((SIDE == 0 && di >= 0) || (SIDE == 1 && di + dj + dk <= 0)) {
       const int ii = i + di, jj = j + dj, kk = k + dk;
       const bool ok = valid && jj >= 0 && kk >= 0 && ii >= 0 && ii + jj + kk <= n;
-      // closure offset: face i = 0, slanted face, or M block (index.hpp)
+      // closure offset: face i = 0, slanted face, or M block (index.hpp);
+      // all candidates computed, then selected (no branch per lane)
       int32_t off;
       if constexpr (SIDE == 0 && di == 0) {
         off = (int32_t)a.off_s0 + t2w32(n + 1, jj, kk);
       } else if constexpr (SIDE == 1 && di + dj + dk == 0) {
         // on the slanted face too; a one-point row (i = 0) lies in S0
-        off = ii == 0 ? (int32_t)a.off_s0 + t2w32(n + 1, jj, kk)
-                      : (int32_t)a.off_s1 + t2w32(n, jj, kk);
+        const int32_t s0 = (int32_t)a.off_s0 + t2w32(n + 1, jj, kk);
+        const int32_t s1 = (int32_t)a.off_s1 + t2w32(n, jj, kk);
+        off = ii == 0 ? s0 : s1;
       } else {
         const int w = n - 1 - kk;
         const int32_t m = tet32(n - 1) - tet32(w) + tri32(w) - tri32(w - jj) + ii - 1;
@@ -205,29 +210,30 @@ __device__ __forceinline__ void p2_face_points(const P2Args& a, int64_t cell,
       acc += wp[t] * xv;
     }
   });
-  if (valid) {
-    T* y = (T*)a.y + cell * a.stride;
-    y[SIDE == 0 ? a.off_s0 + t2w32(n + 1, j, k) : a.off_s1 + t2w32(n, j, k)] = acc;
-  }
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc((T*)a.y + cell * a.stride, bytes);
+  const int el = SIDE == 0 ? (int)a.off_s0 + t2w32(n + 1, j, k) : (int)a.off_s1 + t2w32(n, j, k);
+  bstore(acc, ry, valid ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB);
 }
 
-template <typename T, int SIDE>
+template <typename T, int SIDE, bool UNIFORM>
 __device__ __forceinline__ void p2_face_run(const P2Args& a, int64_t cell, int k,
-                                            int j, int P) {
+                                            int j, bool valid, int P) {
   switch (P) {
-    case 0: p2_face_points<T, 0, SIDE>(a, cell, k, j); break;
-    case 1: p2_face_points<T, 1, SIDE>(a, cell, k, j); break;
-    case 2: p2_face_points<T, 2, SIDE>(a, cell, k, j); break;
-    case 3: p2_face_points<T, 3, SIDE>(a, cell, k, j); break;
-    case 4: p2_face_points<T, 4, SIDE>(a, cell, k, j); break;
-    case 5: p2_face_points<T, 5, SIDE>(a, cell, k, j); break;
-    case 6: p2_face_points<T, 6, SIDE>(a, cell, k, j); break;
-    default: p2_face_points<T, 7, SIDE>(a, cell, k, j); break;
+    case 0: p2_face_points<T, 0, SIDE, UNIFORM>(a, cell, k, j, valid); break;
+    case 1: p2_face_points<T, 1, SIDE, UNIFORM>(a, cell, k, j, valid); break;
+    case 2: p2_face_points<T, 2, SIDE, UNIFORM>(a, cell, k, j, valid); break;
+    case 3: p2_face_points<T, 3, SIDE, UNIFORM>(a, cell, k, j, valid); break;
+    case 4: p2_face_points<T, 4, SIDE, UNIFORM>(a, cell, k, j, valid); break;
+    case 5: p2_face_points<T, 5, SIDE, UNIFORM>(a, cell, k, j, valid); break;
+    case 6: p2_face_points<T, 6, SIDE, UNIFORM>(a, cell, k, j, valid); break;
+    default: p2_face_points<T, 7, SIDE, UNIFORM>(a, cell, k, j, valid); break;
   }
 }
 
-// One wave per run: face SIDE, plane k, lanes j = j0 + 2 lane + s (j0 a
-// multiple of 128), so the node parity is uniform over the wave.
+// One wave per run (make_p2_runs), with a uniform node parity: an interior
+// run holds the points j = 1 + j0 + 2 lane + s (1 <= j <= n - k - 1) of
+// plane k, an edge run the points k = k0 + 2 lane + s of the edge j = 0 or,
+// on face i = 0, of the edge j = n - k (k < n).
 template <typename T>
 __global__ __launch_bounds__(256) void k_p2_face(P2Args a) {
   const int64_t wb = xcd_block(a.nc * a.nfblk);
@@ -237,10 +243,30 @@ __global__ __launch_bounds__(256) void k_p2_face(P2Args a) {
   const int64_t rix = (wb % a.nfblk) * 4 + wave;
   if (rix >= a.nruns) return;
   const int2 run = a.runs[rix];
-  const int k = run.x & 0xffff, side = (run.x >> 16) & 1, s = run.x >> 17;
-  const int j = run.y + 2 * (int)(threadIdx.x & 63) + s;
-  if (side == 0) p2_face_run<T, 0>(a, cell, k, j, (s << 1) | ((k & 1) << 2));
-  else p2_face_run<T, 1>(a, cell, k, j, ((s + k) & 1) | (s << 1) | ((k & 1) << 2));
+  const int n = a.n, lane = (int)(threadIdx.x & 63);
+  const int side = (run.x >> 16) & 1, s = (run.x >> 17) & 1;
+  int j, k;
+  bool valid;
+  const bool interior = ((run.x >> 18) & 1) == 0;
+  if (interior) {
+    k = run.x & 0xffff;
+    j = 1 + run.y + 2 * lane + s;
+    valid = j + k <= n - 1;
+  } else {
+    const int edge = (run.x >> 19) & 1;
+    k = run.y + 2 * lane + s;
+    j = edge ? n - k : 0;
+    valid = side == 0 ? (edge ? k < n : k <= n) : k <= n - 1;
+  }
+  // node parity (n is even): i = 0 on side 0, i = n - j - k on side 1
+  const int sj = j & 1, sk = k & 1;
+  if (interior) {
+    if (side == 0) p2_face_run<T, 0, true>(a, cell, k, j, valid, (sj << 1) | (sk << 2));
+    else p2_face_run<T, 1, true>(a, cell, k, j, valid, ((sj + sk) & 1) | (sj << 1) | (sk << 2));
+  } else {
+    if (side == 0) p2_face_run<T, 0, false>(a, cell, k, j, valid, (sj << 1) | (sk << 2));
+    else p2_face_run<T, 1, false>(a, cell, k, j, valid, ((sj + sk) & 1) | (sj << 1) | (sk << 2));
+  }
 }
 
 template <typename T>
