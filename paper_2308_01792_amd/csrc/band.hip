@@ -83,21 +83,16 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
   __shared__ T ring[kBandSlots * CAP + kBandPad];
   __shared__ T wtab[16 * 15];
   // XCD-aware block order: block b runs on XCD b % 8, and each XCD gets a
-  // contiguous run of the work order.  That order takes the cells in groups
-  // of kGroup and, inside a group, item by item over its cells, so the
-  // neighbouring bands of each cell (whose halo rows and planes overlap)
-  // run close together in time on one XCD and share its L2.
-  constexpr int kGroup = 8;
+  // contiguous run of the (cell, item) work, cell by cell, so the
+  // neighbouring bands of one cell (whose halo rows and planes overlap) run
+  // together on one XCD and share its L2.  (Grouping a few cells item by
+  // item measured slower and read more from HBM.)
   const int64_t nb = a.nblocks;
   const int64_t chunk = (nb + 7) / 8;
   const int64_t wb = (int64_t)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
   if (wb >= nb) return;
-  const int64_t ncell = nb / a.nitems;
-  const int64_t per = (int64_t)kGroup * a.nitems;
-  const int64_t g = wb / per, rem = wb - g * per;
-  const int64_t gc = ncell - g * kGroup < kGroup ? ncell - g * kGroup : kGroup;
-  const int64_t item = rem / gc;
-  const int64_t cell = g * kGroup + (rem - item * gc);
+  const int64_t cell = wb / a.nitems;
+  const int64_t item = wb - cell * a.nitems;
   const int2 it = a.items[item];
   const int j0 = it.x & 0xffff, R = it.x >> 16, k0 = it.y & 0xffff, k1 = it.y >> 16;
   const int lane = threadIdx.x & 63;
