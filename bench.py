@@ -55,6 +55,10 @@ def parse():
     p.add_argument("--cpu-level", type=int, default=5)
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--batch-only-solves", action="store_true",
+                   help="batch leg: only two batched FP32-in-FP64 solves "
+                        "(warm-up, then timed), no loop and no tuning; for a "
+                        "kernel trace of one batched solve")
     p.add_argument("--no-divkgrad", action="store_true")
     p.add_argument("--no-stored", action="store_true")
     p.add_argument("--no-p2", action="store_true")
@@ -69,7 +73,7 @@ def measured_traffic(kernel: str):
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
     kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "cell_apply_box288_l8_traffic.json")
+    path = os.path.join(ROOT, "profiles", "band_apply_box288_l8_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
@@ -83,7 +87,7 @@ def measured_traffic(kernel: str):
     return float(rec["hbm_bytes_per_launch"])
 
 
-def batch_leg(ht, torch):
+def batch_leg(ht, torch, only_solves=False):
     """256 independent small problems (1-24 cells, levels 3-6): one batched
     solve to 1e-10 against a loop of per-problem solves (both after a
     warm-up run that captures graphs and builds the coarse solvers)."""
@@ -119,6 +123,12 @@ def batch_leg(ht, torch):
         torch.cuda.synchronize()
         return us, st, time.time() - t1
 
+    if only_solves:
+        run_batch(ht.HT_PREC_MIXED)
+        _, stb = run_batch(ht.HT_PREC_MIXED)
+        return {"problems": info["problems"], "cells": info["cells"],
+                "dofs": info["dofs"], "mixed_batch_seconds": round(stb[0]["seconds"], 4),
+                "cycles_max": max(x["cycles"] for x in stb)}
     out = {"workload": "256 problems (Kuhn boxes <= 4 cubes, jittered slabs; "
                        "levels 3-6; seed 6), V(2,2) to 1e-10: FP32-in-FP64 "
                        "refinement and FP64",
@@ -574,7 +584,7 @@ def main():
 
     if not args.no_batch:
         log("batched solves of 256 small problems")
-        out["batch"] = batch_leg(ht, torch)
+        out["batch"] = batch_leg(ht, torch, args.batch_only_solves)
         log(f"batch: {json.dumps(out['batch'])}")
 
     if not args.no_cpu:
