@@ -427,19 +427,25 @@ int ht_fmg(ht_mesh* mesh, int level, const ht_cycle_opts* opts, int cycles,
            void* u, const void* b, double* rel_res, ht_stream stream);
 
 /* ------------------------------------------------------------- tuning -- */
-/* The stencil kernel runs one wavefront per tile of 64 i-points x R rows,
+/* The tile kernel runs one wavefront per tile of 64 i-points x R rows,
  * marching in k, four wavefronts per workgroup.  R in {4, 8, 16} trades
- * register pressure against halo re-reads.  ht_set_tile_rows fixes R for
- * the apply and the restriction at (level, dtype) (waves stacked in j);
- * ht_get_tile_rows reports the current choice (default 4). */
+ * register pressure against halo re-reads.  R = 0 selects the band kernel
+ * (whole rows of a cell staged plane by plane in LDS), available up to the
+ * level where a band of four rows still fits its LDS image (level 8).
+ * ht_set_tile_rows fixes R for the apply and the restriction at (level,
+ * dtype) (the restriction takes R = 4 when the apply takes the band
+ * kernel); ht_get_tile_rows reports the current choice (default: the band
+ * kernel where it is available, else 4). */
 int ht_set_tile_rows(ht_mesh* mesh, int level, int dtype, int rows);
 int ht_get_tile_rows(const ht_mesh* mesh, int level, int dtype, int* rows);
 /* Tile shape of the sweep operations (residual, Jacobi, FP32 residual,
  * Chebyshev step), which also stream b: R rows per wave and the workgroup's
  * arrangement, waves_in_i = 1 for its four waves side by side in i (one
- * contiguous run of 248 points per row), 0 for stacked in j.  Default
- * R = 4, waves_in_i = 1 from level 8 on (0 below).  Results do not depend
- * on the shape. */
+ * contiguous run of 248 points per row), 0 for stacked in j.  R = 0 runs
+ * the Jacobi sweep and the residual on the band kernel (the FP32 residual
+ * and the Chebyshev step then use R = 4) where it is available.  Default:
+ * the band kernel from level 7 on, else R = 4; waves_in_i = 1 from level 8
+ * on (0 below).  Results do not depend on the shape (up to rounding). */
 int ht_set_sweep_shape(ht_mesh* mesh, int level, int dtype, int rows,
                        int waves_in_i);
 int ht_get_sweep_shape(const ht_mesh* mesh, int level, int dtype, int* rows,

@@ -231,6 +231,12 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
 
   // ------------------------------------------------------ compute waves --
   const __amdgpu_buffer_rsrc_t ry = make_rsrc((T*)a.y + cell * a.stride, bytes);
+  constexpr bool SWEEP = OP == OP_JACOBI || OP == OP_RESID;
+  const __amdgpu_buffer_rsrc_t rb =
+      make_rsrc(SWEEP ? (const T*)a.b + cell * a.stride : (const T*)a.x, SWEEP ? bytes : 0);
+  // omega D^-1 at the cell's interior points (as the tile kernel forms it)
+  const T omega_invd = SWEEP ? (T)(a.omega * a.nscale * a.cls[cell * 16].inv_diag_unit) : (T)0;
+  double nsq = 0.0;  // |r|^2 of the points this wave finishes
   const T w0 = wc[0], w1 = wc[1], w2 = wc[2], w3 = wc[3], w4 = wc[4], w5 = wc[5],
           w6 = wc[6], w7 = wc[7], w8 = wc[8], w9 = wc[9], w10 = wc[10],
           w11 = wc[11], w12 = wc[12], w13 = wc[13], w14 = wc[14];
@@ -307,6 +313,24 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
       const int r = 2 * p + 1, c = u - Ep;
       const int A = bstart(r, L0) + c;
       const int v = L0 - r + 2;  // positions of image row r
+      // main-block points only (2 <= c <= L_r - 1); the row ends are the
+      // face points computed below.  Row r + 1 is one point shorter.
+      const bool out = lane >= 1 && lane <= 62 && ur == u;
+      const bool two = out && r + 1 <= rmax;
+      const int Lr = L0 - r;
+      const unsigned sz = (unsigned)sizeof(T);
+      const unsigned e1 = (unsigned)(Kc + A - 4 * r) * sz;
+      const unsigned e2 = e1 + (unsigned)(v - 4) * sz;
+      const bool st1a = out && c >= 2 && c <= Lr - 1, st1b = out && c >= 1 && c <= Lr - 2;
+      const bool st2a = two && c >= 2 && c <= Lr - 2, st2b = two && c >= 1 && c <= Lr - 3;
+      // sweeps: b at the four points, two 16-byte loads issued before the
+      // LDS reads (a pair's second value is read even where only the first
+      // is used: it is the next main-block element, inside the cell block)
+      u32x4 bv1 = {0u, 0u, 0u, 0u}, bv2 = {0u, 0u, 0u, 0u};
+      if constexpr (SWEEP) {
+        bv1 = __builtin_amdgcn_raw_buffer_load_b128(rb, (st1a || st1b) ? e1 : HT_OOB, 0, 0);
+        bv2 = __builtin_amdgcn_raw_buffer_load_b128(rb, (st2a || st2b) ? e2 : HT_OOB, 0, 0);
+      }
       // ten rows (dj, dk) at columns A, A + 1: plane k rows r - 1 .. r + 2,
       // plane k + 1 rows r - 1 .. r + 1, plane k - 1 rows r .. r + 2
       const int q0 = sk + A, q1 = q0 + v, q2 = q1 + v - 1, qm = q0 - v - 1;
@@ -324,19 +348,29 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
         row_special(wtab + 15 * (((jm + r == 0) << 1) | kb), K0, K1, Km, P0, Pm, M0, M1, a1, b1);
         row_special(wtab + 15 * kb, K1, K2, K0, P1, P0, M1, M2, a2, b2);
       }
-      // main-block points only (2 <= c <= L_r - 1); the row ends are the
-      // face points computed below.  Row r + 1 is one point shorter.
-      const bool out = lane >= 1 && lane <= 62 && ur == u;
-      const bool two = out && r + 1 <= rmax;
-      const int Lr = L0 - r;
-      const unsigned sz = (unsigned)sizeof(T);
-      const unsigned e1 = (unsigned)(Kc + A - 4 * r) * sz;
-      const unsigned e2 = e1 + (unsigned)(v - 4) * sz;
+      if constexpr (SWEEP) {
+        // Points on the faces j = 0 (row 1 of the band j0 = 0) and k = 0
+        // keep their partial row for the exchange; the others are finished:
+        // r = b - A u, and the Jacobi update u + omega D^-1 r or r itself.
+        const bool surf1 = SPECIAL && ((jm + r == 0) || k == 0);
+        const bool surf2 = SPECIAL && k == 0;
+        const T* b1v = reinterpret_cast<const T*>(&bv1);
+        const T* b2v = reinterpret_cast<const T*>(&bv2);
+        auto fin = [&](T acc, T xc, T bval, bool st, bool surf) {
+          const T rr = bval - acc;
+          nsq += (st && !surf) ? (double)rr * (double)rr : 0.0;
+          return surf ? acc : (OP == OP_JACOBI ? fma(omega_invd, rr, xc) : rr);
+        };
+        a1 = fin(a1, K0.a, b1v[0], st1a, surf1);
+        b1 = fin(b1, K0.b, b1v[1], st1b, surf1);
+        a2 = fin(a2, K1.a, b2v[0], st2a, surf2);
+        b2 = fin(b2, K1.b, b2v[1], st2b, surf2);
+      }
       // no branches: the chunk stays one basic block
-      bstore(a1, ry, out && c >= 2 && c <= Lr - 1 ? e1 : HT_OOB);
-      bstore(b1, ry, out && c >= 1 && c <= Lr - 2 ? e1 + sz : HT_OOB);
-      bstore(a2, ry, two && c >= 2 && c <= Lr - 2 ? e2 : HT_OOB);
-      bstore(b2, ry, two && c >= 1 && c <= Lr - 3 ? e2 + sz : HT_OOB);
+      bstore(a1, ry, st1a ? e1 : HT_OOB);
+      bstore(b1, ry, st1b ? e1 + sz : HT_OOB);
+      bstore(a2, ry, st2a ? e2 : HT_OOB);
+      bstore(b2, ry, st2b ? e2 + sz : HT_OOB);
     };
     // chunks before nspec may touch row 1 of the band j0 = 0 (pair 0, whose
     // first row ends below E(1) = b - 1); on the plane k = 0 every chunk is
@@ -385,6 +419,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
     if (k < k1) compute(k);
     lds_barrier();
   }
+  if constexpr (SWEEP) {
+    nsq = wave_sum(nsq);
+    if (lane == 0) a.partials[wb * kBandComputeWaves + wave] = nsq;
+  }
 }
 
 template <typename T>
@@ -393,6 +431,12 @@ static void launch_band_t(int op, const BandArgs& a, hipStream_t s) {
   switch (op) {
     case OP_APPLY:
       hipLaunchKernelGGL((k_band<T, OP_APPLY>), grid, dim3(kBandThreads), 0, s, a);
+      break;
+    case OP_JACOBI:
+      hipLaunchKernelGGL((k_band<T, OP_JACOBI>), grid, dim3(kBandThreads), 0, s, a);
+      break;
+    case OP_RESID:
+      hipLaunchKernelGGL((k_band<T, OP_RESID>), grid, dim3(kBandThreads), 0, s, a);
       break;
     default: throw Error{HT_ERR_ARG, "band kernel: unsupported operation"};
   }

@@ -168,12 +168,21 @@ inline void make_band_rowtab(int level, int cap, int esize, const std::vector<in
   }
 }
 
+struct ClassInfo;
+
 struct BandArgs {
-  const void* x;     // operand
+  const void* x;     // operand (the iterate u of the sweeps)
   void* y;           // output (partial rows at surface points)
   const void* w;     // level-scaled class stencils [nc][16][15]
   const int2* items; // work items of one cell
   const uint8_t* rtab;  // row table of the level (make_band_rowtab)
+  // Jacobi sweep and residual (OP_JACOBI, OP_RESID): right-hand side, the
+  // cells' class data (inverse diagonal), one norm partial per compute wave
+  // (|r|^2 of the points the wave finishes), omega and the level scale
+  const void* b;
+  const ClassInfo* cls;
+  double* partials;
+  double omega, nscale;
   int64_t nitems, nblocks;
   int64_t stride, off_s0, off_s1;
   int n;

@@ -173,6 +173,69 @@ def test_jacobi_sweeps(name, level, sweeps):
         assert rel_err(P.from_gpu(level, ug), S.jacobi(u0, b, 2.0 / 3.0, sweeps)) <= tol
 
 
+@pytest.mark.parametrize("name,level,sweeps", [("jittered_288", 4, 3),
+                                               ("ref_tet", 5, 2),
+                                               ("kuhn_211", 4, 2),
+                                               ("slab_3_11", 3, 1),
+                                               ("jittered_222", 5, 2)])
+def test_band_sweeps_match_oracle(name, level, sweeps):
+    """The Jacobi sweep and the residual (with its norm) from the band kernel
+    (sweep rows 0): finished points updated in the kernel, points on the cell
+    faces completed by the exchange."""
+    P = pair(name, level, level)
+    S = P.S(level)
+    N = S.mesh.num_vertices
+    u0 = fields.uniform_values(N, 7)        # non-zero Dirichlet data kept
+    b = fields.uniform_values(N, 8)
+    for dtype, code, tol in ((torch.float64, ht.HT_F64, FP64_TOL),
+                             (torch.float32, ht.HT_F32, 20 * FP32_TOL)):
+        old = P.m.sweep_shape(level, code)
+        P.m.set_sweep_shape(level, code, 0, old[1])
+        try:
+            assert P.m.sweep_shape(level, code)[0] == 0
+            ug = P.to_gpu(level, u0, dtype)
+            bg = P.to_gpu(level, b, dtype)
+            P.m.smooth_jacobi(level, ug, bg, 2.0 / 3.0, sweeps)
+            assert rel_err(P.from_gpu(level, ug), S.jacobi(u0, b, 2.0 / 3.0, sweeps)) <= tol
+            r = torch.zeros_like(bg)
+            nrm = P.m.residual(level, P.to_gpu(level, u0, dtype), bg, r, want_norm=True)
+            ref = S.residual(u0, b)
+            assert rel_err(P.from_gpu(level, r), ref) <= tol
+            assert abs(nrm - np.linalg.norm(ref)) <= tol * np.linalg.norm(ref)
+        finally:
+            P.m.set_sweep_shape(level, code, old[0], old[1])
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_band_and_tile_sweeps_agree_at_level_7(dt):
+    """Band and tile Jacobi sweeps and residuals on the 288-cell box at level
+    7 (no oracle at this size): the same values to rounding."""
+    L = 7
+    m = ht.Mesh(*mesh_by_name("jittered_288"), 2, L)
+    code = ht.HT_F64 if dt == torch.float64 else ht.HT_F32
+    rng = np.random.default_rng(9)
+    n = m.n_slots(L)
+    u0 = torch.tensor(rng.uniform(-1, 1, n), dtype=dt, device="cuda")
+    b = torch.tensor(rng.uniform(-1, 1, n), dtype=dt, device="cuda")
+    m.sync(L, u0)
+    m.sync(L, b)
+    outs = []
+    for rows in (0, 4):
+        m.set_sweep_shape(L, code, rows, True)
+        u = u0.clone()
+        m.smooth_jacobi(L, u, b, sweeps=2)
+        r = torch.zeros_like(u)
+        nr = m.residual(L, u, b, r, want_norm=True)
+        outs.append((u, r, nr))
+    (ub, rb, nb), (ut, rt, nt) = outs
+    tol = FP64_TOL if dt == torch.float64 else 20 * FP32_TOL
+    scale = float(ut.abs().max())
+    assert float((ub - ut).abs().max()) <= tol * scale
+    assert float((rb - rt).abs().max()) <= tol * float(rt.abs().max())
+    assert abs(nb - nt) <= tol * nt
+    m.close()
+
+
 @pytest.mark.parametrize("name,fine", [("jittered_288", 3), ("jittered_288", 4),
                                        ("ref_tet", 4), ("slab_3_11", 3),
                                        ("kuhn_211", 2), ("jittered_222", 1)])
@@ -379,7 +442,7 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     rows = P.m.autotune(4, ht.HT_F64, cache)
     assert rows in (0, 4, 8, 16) and P.m.tile_rows(4, ht.HT_F64) == rows
     sweep = P.m.sweep_shape(4, ht.HT_F64)
-    assert sweep[0] in (4, 8, 16)
+    assert sweep[0] in (0, 4, 8, 16)   # 0: the band kernel
     P.m.set_tile_rows(4, ht.HT_F64, 4 if rows != 4 else 8)
     P.m.set_sweep_shape(4, ht.HT_F64, 16 if sweep[0] != 16 else 8,
                         not sweep[1])
