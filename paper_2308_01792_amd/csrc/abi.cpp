@@ -342,7 +342,10 @@ struct Shape {
   int seg;        // planes per march segment
 };
 // operations the band kernel runs
-static bool band_op(int op) { return op == OP_APPLY || op == OP_JACOBI || op == OP_RESID; }
+static bool band_op(int op) {
+  return op == OP_APPLY || op == OP_JACOBI || op == OP_RESID || op == OP_RESID32 ||
+         op == OP_RESID32X;
+}
 // untuned sweeps use the band kernel from this level on (measured at level 8:
 // Jacobi 4.22 against 4.94 ms in FP64, 2.49 against 2.78 ms in FP32); below,
 // where the kernels are short, the tile kernel
@@ -485,15 +488,20 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
   if (!norm_dst) norm_dst = m.d_scalar + scalar_slot;
   const Shape sh = choose_shape(h, level, dtype, op);
   if (sh.J == 0 && band_op(op)) {
-    const BandArgs ba = band_args(h, level, dtype, x, y, R, b, omega, partials);
+    BandArgs ba = band_args(h, level, dtype, x, y, R, b, omega, partials);
+    ba.y32 = (float*)at_cell(y32, R.c0, level, HT_F32);
+    if (fuse) ba.efirst = (float*)at_cell(fuse->efirst, R.c0, level, HT_F32);
+    const bool res = op == OP_RESID || op == OP_RESID32 || op == OP_RESID32X;
     {
-      Prof p(h, op == OP_APPLY ? "cell_apply" : op == OP_RESID ? "cell_residual" : "cell_jacobi", s);
+      Prof p(h, op == OP_APPLY ? "cell_apply" : res ? "cell_residual" : "cell_jacobi", s);
       launch_band(dtype, op, ba, s);
       check_launch();
     }
     ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
                             partials + kBandComputeWaves * ba.nblocks, R);
-    if (op == OP_RESID) ea.u = x;
+    if (res) ea.u = x;
+    ea.y32 = y32;
+    if (fuse) ea.efirst = fuse->efirst;
     if (ea.total > 0) {
       Prof p(h, "exchange", s);
       launch_exchange(dtype, op, ea, s);

@@ -231,7 +231,13 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
 
   // ------------------------------------------------------ compute waves --
   const __amdgpu_buffer_rsrc_t ry = make_rsrc((T*)a.y + cell * a.stride, bytes);
-  constexpr bool SWEEP = OP == OP_JACOBI || OP == OP_RESID;
+  constexpr bool R32 = OP == OP_RESID32 || OP == OP_RESID32X;
+  constexpr bool SWEEP = OP == OP_JACOBI || OP == OP_RESID || R32;
+  const __amdgpu_buffer_rsrc_t ry32 =
+      make_rsrc(R32 ? a.y32 + cell * a.stride : (float*)a.y, R32 ? a.stride * 4 : 0);
+  const __amdgpu_buffer_rsrc_t ref =
+      make_rsrc(OP == OP_RESID32X ? a.efirst + cell * a.stride : (float*)a.y,
+                OP == OP_RESID32X ? a.stride * 4 : 0);
   const __amdgpu_buffer_rsrc_t rb =
       make_rsrc(SWEEP ? (const T*)a.b + cell * a.stride : (const T*)a.x, SWEEP ? bytes : 0);
   // omega D^-1 at the cell's interior points (as the tile kernel forms it)
@@ -356,15 +362,35 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
         const bool surf2 = SPECIAL && k == 0;
         const T* b1v = reinterpret_cast<const T*>(&bv1);
         const T* b2v = reinterpret_cast<const T*>(&bv2);
-        auto fin = [&](T acc, T xc, T bval, bool st, bool surf) {
+        auto fin = [&](T acc, T xc, T bval, bool st, bool surf, unsigned e) {
           const T rr = bval - acc;
           nsq += (st && !surf) ? (double)rr * (double)rr : 0.0;
+          if constexpr (R32) {
+            // finished points: the FP32 residual (element offset = e / 2)
+            // and, fused, the next correction's first sweep in FP32 as the
+            // separate zero-guess sweep forms it (FP32 factor times FP32
+            // residual); the face points' FP64 partial rows are stored below
+            const unsigned f = (st && !surf) ? e >> 1 : HT_OOB;
+            bstore((float)rr, ry32, f);
+            if constexpr (OP == OP_RESID32X) bstore((float)omega_invd * (float)rr, ref, f);
+            return acc;
+          }
           return surf ? acc : (OP == OP_JACOBI ? fma(omega_invd, rr, xc) : rr);
         };
-        a1 = fin(a1, K0.a, b1v[0], st1a, surf1);
-        b1 = fin(b1, K0.b, b1v[1], st1b, surf1);
-        a2 = fin(a2, K1.a, b2v[0], st2a, surf2);
-        b2 = fin(b2, K1.b, b2v[1], st2b, surf2);
+        a1 = fin(a1, K0.a, b1v[0], st1a, surf1, e1);
+        b1 = fin(b1, K0.b, b1v[1], st1b, surf1, e1 + sz);
+        a2 = fin(a2, K1.a, b2v[0], st2a, surf2, e2);
+        b2 = fin(b2, K1.b, b2v[1], st2b, surf2, e2 + sz);
+        if constexpr (R32) {
+          // only the face points keep an FP64 partial row
+          if constexpr (SPECIAL) {
+            bstore(a1, ry, st1a && surf1 ? e1 : HT_OOB);
+            bstore(b1, ry, st1b && surf1 ? e1 + sz : HT_OOB);
+            bstore(a2, ry, st2a && surf2 ? e2 : HT_OOB);
+            bstore(b2, ry, st2b && surf2 ? e2 + sz : HT_OOB);
+          }
+          return;
+        }
       }
       // no branches: the chunk stays one basic block
       bstore(a1, ry, st1a ? e1 : HT_OOB);
@@ -438,6 +464,16 @@ static void launch_band_t(int op, const BandArgs& a, hipStream_t s) {
     case OP_RESID:
       hipLaunchKernelGGL((k_band<T, OP_RESID>), grid, dim3(kBandThreads), 0, s, a);
       break;
+    case OP_RESID32:
+    case OP_RESID32X:
+      if constexpr (sizeof(T) == 8) {
+        if (op == OP_RESID32)
+          hipLaunchKernelGGL((k_band<T, OP_RESID32>), grid, dim3(kBandThreads), 0, s, a);
+        else
+          hipLaunchKernelGGL((k_band<T, OP_RESID32X>), grid, dim3(kBandThreads), 0, s, a);
+        break;
+      }
+      throw Error{HT_ERR_ARG, "band kernel: the FP32-output residual is an FP64 operation"};
     default: throw Error{HT_ERR_ARG, "band kernel: unsupported operation"};
   }
 }

@@ -183,6 +183,11 @@ struct BandArgs {
   const ClassInfo* cls;
   double* partials;
   double omega, nscale;
+  // FP64 residual with FP32 outputs (OP_RESID32, OP_RESID32X): r in FP32 at
+  // the finished points (y then holds the partial rows of the others), and
+  // for OP_RESID32X the next correction's first Jacobi sweep omega D^-1 r
+  float* y32;
+  float* efirst;
   int64_t nitems, nblocks;
   int64_t stride, off_s0, off_s1;
   int n;
