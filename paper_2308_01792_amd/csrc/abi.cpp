@@ -68,6 +68,7 @@ struct ht_mesh {
   // (fine level, J) -> P2 k-march segments; fine level -> P2 face runs
   std::map<std::pair<int, int>, std::pair<int2*, int64_t>> p2_tiles;
   std::map<int, std::pair<int2*, int64_t>> p2_runs;
+  std::map<int, std::pair<int2*, int64_t>> p2_face_tiles;
   // P2 level -> subgroup rows (g, k, j, element offset) of one cell
   std::map<int, std::pair<int4*, int64_t>> p2_pack_rows;
   bool capturing = false;
@@ -678,30 +679,29 @@ static std::vector<int2> make_p2_columns(int n, int J, int seg) {
     }
   return t;
 }
-// Face runs of one cell, for the points of face i = 0 (side 0, j + k <= n)
-// and of the slanted face (side 1, j + k <= n - 1), 64 points of one node
-// parity per run:
-//   interior runs (k | side << 16 | s << 17, j0): the points
-//     j = 1 + j0 + 2 lane + s of plane k with 1 <= j <= n - k - 1, which
-//     share one boundary class;
-//   edge runs (side << 16 | s << 17 | 1 << 18 | edge << 19, k0): the points
+// Face work of one cell (faces i = 0, side 0, and i = n - j - k, side 1):
+//   face tiles (k0 | side << 16, jb): the points of the rows
+//     1 <= j <= n - k - 1 of the planes k0 .. k0 + kP2FaceK - 1, rows
+//     jb .. jb + kP2FaceRows - 1, which share one boundary class per plane;
+//   edge runs (side << 16 | s << 17 | edge << 19, k0): the 64 points
 //     k = k0 + 2 lane + s of the edge j = 0 (edge 0) or, on face i = 0, of
 //     the edge j = n - k with k < n (edge 1), each with its own class.
-static std::vector<int2> make_p2_runs(int n) {
+static std::vector<int2> make_p2_face_tiles(int n) {
   std::vector<int2> t;
-  for (int k = 0; k <= n; ++k)
-    for (int side = 0; side < 2; ++side) {
-      const int jmax = n - k - 1;  // interior rows: 1 <= j <= n - k - 1
-      for (int j0 = 0; 1 + j0 <= jmax; j0 += 128)
-        for (int s = 0; s < 2 && 1 + j0 + s <= jmax; ++s)
-          t.push_back(make_int2(k | (side << 16) | (s << 17), j0));
-    }
+  for (int side = 0; side < 2; ++side)
+    for (int k0 = 0; k0 <= n - 2; k0 += kP2FaceK)
+      for (int jb = 0; jb <= n - k0 - 1; jb += kP2FaceRows)
+        t.push_back(make_int2(k0 | (side << 16), jb));
+  return t;
+}
+static std::vector<int2> make_p2_edge_runs(int n) {
+  std::vector<int2> t;
   for (int side = 0; side < 2; ++side)
     for (int edge = 0; edge < (side == 0 ? 2 : 1); ++edge) {
       const int kmax = side == 0 ? (edge ? n - 1 : n) : n - 1;
       for (int k0 = 0; k0 <= kmax; k0 += 128)
         for (int s = 0; s < 2 && k0 + s <= kmax; ++s)
-          t.push_back(make_int2((side << 16) | (s << 17) | (1 << 18) | (edge << 19), k0));
+          t.push_back(make_int2((side << 16) | (s << 17) | (edge << 19), k0));
     }
   return t;
 }
@@ -723,8 +723,13 @@ static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   }
   auto runs = h->p2_runs.find(lf);
   if (runs == h->p2_runs.end()) {
-    auto t = make_p2_runs(L.n);
+    auto t = make_p2_edge_runs(L.n);
     runs = h->p2_runs.emplace(lf, std::make_pair(upload(t), (int64_t)t.size())).first;
+  }
+  auto ftiles = h->p2_face_tiles.find(lf);
+  if (ftiles == h->p2_face_tiles.end()) {
+    auto t = make_p2_face_tiles(L.n);
+    ftiles = h->p2_face_tiles.emplace(lf, std::make_pair(upload(t), (int64_t)t.size())).first;
   }
   P2Args a{};
   a.x = x; a.y = y;
@@ -732,6 +737,8 @@ static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   a.tiles = tiles->second.first;
   a.ntiles = tiles->second.second;
   a.nblk = (a.ntiles + 3) / 4;
+  a.ftiles = ftiles->second.first;
+  a.nftiles = ftiles->second.second;
   a.runs = runs->second.first;
   a.nruns = runs->second.second;
   a.nfblk = (a.nruns + 3) / 4;
@@ -742,6 +749,7 @@ static void p2_pass(ht_mesh* h, int level, int dtype, const void* x, void* y,
   {
     P2Args b = a;  // bulk kernel only
     b.nfblk = 0;
+    b.nftiles = 0;
     Prof p(h, "cell_p2", s);
     launch_p2(dtype, J, b, s);
     check_launch();
@@ -1316,6 +1324,7 @@ int ht_mesh_destroy(ht_mesh* h) {
       for (auto* p : m.d_p2w32) if (p) (void)hipFree(p);
       for (auto& kv : h->p2_tiles) (void)hipFree(kv.second.first);
       for (auto& kv : h->p2_runs) (void)hipFree(kv.second.first);
+      for (auto& kv : h->p2_face_tiles) (void)hipFree(kv.second.first);
       for (auto& kv : h->p2_pack_rows) (void)hipFree(kv.second.first);
       for (auto* list : {&m.work64, &m.work32})
         for (auto& w : *list) {

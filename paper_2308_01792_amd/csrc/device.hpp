@@ -77,6 +77,31 @@ __device__ __forceinline__ RowBase row_base(const Lay& L, int j, int k) {
   r.m = (int32_t)tw32(n - 1, 0, j, k);
   return r;
 }
+// The same bases from per-plane parts: row (j, k) starts at
+// m = pm - tri32(n - 1 - k - j) in M and at ps0 + j, ps1 + j in S0 and S1,
+// so a wave walking the rows of a plane forms the plane part once.  Rows
+// outside the plane (j < 0 or j + k > n) get offsets that are never used.
+struct PlaneBase {
+  int k;
+  int32_t pm, ps0, ps1;
+};
+__device__ __forceinline__ PlaneBase plane_base(const Lay& L, int k) {
+  const int n = L.n, w = n - 1;
+  PlaneBase p;
+  p.k = k;
+  p.pm = tet32(w) - tet32(w - k) + tri32(w - k);
+  p.ps0 = (int32_t)L.off_s0 + tri32(n + 1) - tri32(n + 1 - k);
+  p.ps1 = (int32_t)L.off_s1 + tri32(n) - tri32(n - k);
+  return p;
+}
+__device__ __forceinline__ RowBase row_base(const Lay& L, const PlaneBase& p, int j) {
+  RowBase r;
+  r.e = L.n - j - p.k;
+  r.s0 = p.ps0 + j;
+  r.s1 = p.ps1 + j;
+  r.m = p.pm - tri32(L.n - 1 - p.k - j);
+  return r;
+}
 __device__ __forceinline__ int32_t row_slot(const RowBase& r, int i) {
   return i == 0 ? r.s0 : (i == r.e ? r.s1 : r.m + i - 1);
 }

@@ -58,11 +58,21 @@ __device__ __forceinline__ void p2_load_plane(T (&xp)[J + 4][2],
                                               int i0, int lane) {
   const int n = L.n;
   const bool pv = kk >= 0 && kk <= n;
+  const PlaneBase pb = plane_base(L, kk);
+  // M offsets of consecutive rows: tri32(a - 1) = tri32(a) - max(a, 0)
+  int a = n - 1 - kk - (j0 - 2);
+  int ta = tri32(a);
 #pragma unroll
   for (int rr = 0; rr < J + 4; ++rr) {
     const int jj = j0 - 2 + rr;
     const bool rv = pv && jj >= 0 && jj + kk <= n;
-    const RowBase rb = row_base(L, rv ? jj : 0, rv ? kk : 0);
+    RowBase rb;
+    rb.e = n - jj - kk;
+    rb.s0 = pb.ps0 + jj;
+    rb.s1 = pb.ps1 + jj;
+    rb.m = pb.pm - ta;
+    ta -= a > 0 ? a : 0;
+    --a;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int ii = i0 + 2 * lane + c;
@@ -130,11 +140,12 @@ __device__ __forceinline__ void p2_march_column(const P2Args& a, int64_t cell,
           });
         });
       });
+      const PlaneBase pk = plane_base(L, k);
 #pragma unroll
       for (int r = 0; r < J; ++r) {
         const int j = j0 + r;
         const int e = n - j - k;
-        const RowBase rb = row_base(L, e >= 0 ? j : 0, k);
+        const RowBase rb = row_base(L, pk, j);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           const T v = acc[r][c][1] + lane_next(acc[r][c][2]) + lane_prev(acc[r][c][0]);
@@ -149,7 +160,7 @@ __device__ __forceinline__ void p2_march_column(const P2Args& a, int64_t cell,
 }
 
 template <typename T, int J>
-__global__ __launch_bounds__(256) void k_p2_march(P2Args a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_p2_march(P2Args a) {
   const int64_t wb = xcd_block(a.nc * a.nblk);
   if (wb >= a.nc * a.nblk) return;
   const int64_t cell = wb / a.nblk;
@@ -162,23 +173,20 @@ __global__ __launch_bounds__(256) void k_p2_march(P2Args a) {
   else p2_march_column<T, J, 0>(a, cell, j0, tl.y, k0);
 }
 
-// Points of one face of one cell for one parity class: SIDE 0 is the face
-// i = 0 (S0), SIDE 1 the face i = n - j - k (S1, points with i >= 1).  The
-// stencil is unrolled at compile time; entries that always have zero weight
-// on that face (di < 0 on i = 0, di + dj + dk > 0 on the slanted face) are
-// dropped, so every remaining neighbour lies inside the closure whenever its
-// row exists.  UNIFORM: every valid lane has the boundary class of lane 0
-// (the interior rows of a face), so the stencil weights are read once per
-// wave (scalar loads) instead of once per lane.
-template <typename T, int P, int SIDE, bool UNIFORM>
-__device__ __forceinline__ void p2_face_points(const P2Args& a, int64_t cell,
+// Edge points of one face of one cell for one parity class: SIDE 0 is the
+// face i = 0 (S0), SIDE 1 the face i = n - j - k (S1, points with i >= 1);
+// each lane has its own boundary class.  The stencil is unrolled at compile
+// time; entries that always have zero weight on that face (di < 0 on i = 0,
+// di + dj + dk > 0 on the slanted face) are dropped, so every remaining
+// neighbour lies inside the closure whenever its row exists.
+template <typename T, int P, int SIDE>
+__device__ __forceinline__ void p2_edge_points(const P2Args& a, int64_t cell,
                                                int k, int j, bool valid) {
   const int n = a.n;
   const int i = SIDE == 0 ? 0 : n - j - k;
   const int64_t bytes = a.stride * (int64_t)sizeof(T);
   const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
-  const int cls = UNIFORM ? __builtin_amdgcn_readfirstlane(point_class(n, i, j, k))
-                          : point_class(n, i, j, k);
+  const int cls = point_class(n, i, j, k);
   const T* wp = (const T*)a.w + cell * (int64_t)kP2PerCell +
                 (P * kNumClasses + cls) * kP2MaxOffsets;
   T acc = 0;
@@ -215,27 +223,26 @@ __device__ __forceinline__ void p2_face_points(const P2Args& a, int64_t cell,
   bstore(acc, ry, valid ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB);
 }
 
-template <typename T, int SIDE, bool UNIFORM>
-__device__ __forceinline__ void p2_face_run(const P2Args& a, int64_t cell, int k,
+template <typename T, int SIDE>
+__device__ __forceinline__ void p2_edge_run(const P2Args& a, int64_t cell, int k,
                                             int j, bool valid, int P) {
   switch (P) {
-    case 0: p2_face_points<T, 0, SIDE, UNIFORM>(a, cell, k, j, valid); break;
-    case 1: p2_face_points<T, 1, SIDE, UNIFORM>(a, cell, k, j, valid); break;
-    case 2: p2_face_points<T, 2, SIDE, UNIFORM>(a, cell, k, j, valid); break;
-    case 3: p2_face_points<T, 3, SIDE, UNIFORM>(a, cell, k, j, valid); break;
-    case 4: p2_face_points<T, 4, SIDE, UNIFORM>(a, cell, k, j, valid); break;
-    case 5: p2_face_points<T, 5, SIDE, UNIFORM>(a, cell, k, j, valid); break;
-    case 6: p2_face_points<T, 6, SIDE, UNIFORM>(a, cell, k, j, valid); break;
-    default: p2_face_points<T, 7, SIDE, UNIFORM>(a, cell, k, j, valid); break;
+    case 0: p2_edge_points<T, 0, SIDE>(a, cell, k, j, valid); break;
+    case 1: p2_edge_points<T, 1, SIDE>(a, cell, k, j, valid); break;
+    case 2: p2_edge_points<T, 2, SIDE>(a, cell, k, j, valid); break;
+    case 3: p2_edge_points<T, 3, SIDE>(a, cell, k, j, valid); break;
+    case 4: p2_edge_points<T, 4, SIDE>(a, cell, k, j, valid); break;
+    case 5: p2_edge_points<T, 5, SIDE>(a, cell, k, j, valid); break;
+    case 6: p2_edge_points<T, 6, SIDE>(a, cell, k, j, valid); break;
+    default: p2_edge_points<T, 7, SIDE>(a, cell, k, j, valid); break;
   }
 }
 
-// One wave per run (make_p2_runs), with a uniform node parity: an interior
-// run holds the points j = 1 + j0 + 2 lane + s (1 <= j <= n - k - 1) of
-// plane k, an edge run the points k = k0 + 2 lane + s of the edge j = 0 or,
-// on face i = 0, of the edge j = n - k (k < n).
+// One wave per edge run (make_p2_edge_runs), with a uniform node parity: the
+// points k = k0 + 2 lane + s of the edge j = 0 or, on face i = 0, of the
+// edge j = n - k (k < n).
 template <typename T>
-__global__ __launch_bounds__(256) void k_p2_face(P2Args a) {
+__global__ __launch_bounds__(256) void k_p2_edge(P2Args a) {
   const int64_t wb = xcd_block(a.nc * a.nfblk);
   if (wb >= a.nc * a.nfblk) return;
   const int64_t cell = wb / a.nfblk;
@@ -245,27 +252,137 @@ __global__ __launch_bounds__(256) void k_p2_face(P2Args a) {
   const int2 run = a.runs[rix];
   const int n = a.n, lane = (int)(threadIdx.x & 63);
   const int side = (run.x >> 16) & 1, s = (run.x >> 17) & 1;
-  int j, k;
-  bool valid;
-  const bool interior = ((run.x >> 18) & 1) == 0;
-  if (interior) {
-    k = run.x & 0xffff;
-    j = 1 + run.y + 2 * lane + s;
-    valid = j + k <= n - 1;
-  } else {
-    const int edge = (run.x >> 19) & 1;
-    k = run.y + 2 * lane + s;
-    j = edge ? n - k : 0;
-    valid = side == 0 ? (edge ? k < n : k <= n) : k <= n - 1;
-  }
+  const int edge = (run.x >> 19) & 1;
+  const int k = run.y + 2 * lane + s;
+  const int j = edge ? n - k : 0;
+  const bool valid = side == 0 ? (edge ? k < n : k <= n) : k <= n - 1;
   // node parity (n is even): i = 0 on side 0, i = n - j - k on side 1
   const int sj = j & 1, sk = k & 1;
-  if (interior) {
-    if (side == 0) p2_face_run<T, 0, true>(a, cell, k, j, valid, (sj << 1) | (sk << 2));
-    else p2_face_run<T, 1, true>(a, cell, k, j, valid, ((sj + sk) & 1) | (sj << 1) | (sk << 2));
-  } else {
-    if (side == 0) p2_face_run<T, 0, false>(a, cell, k, j, valid, (sj << 1) | (sk << 2));
-    else p2_face_run<T, 1, false>(a, cell, k, j, valid, ((sj + sk) & 1) | (sj << 1) | (sk << 2));
+  if (side == 0) p2_edge_run<T, 0>(a, cell, k, j, valid, (sj << 1) | (sk << 2));
+  else p2_edge_run<T, 1>(a, cell, k, j, valid, ((sj + sk) & 1) | (sj << 1) | (sk << 2));
+}
+
+// ------------------------------------------------------- face tiles --
+// The face points of the rows 1 <= j <= n - k - 1 of kP2FaceK planes, for
+// kP2FaceRows rows from jb.  The stencil of a point on face i = 0 reaches the
+// first three points of the rows j - 2 .. j + 2 of the planes k - 2 .. k + 2
+// (di = 0, 1, 2), and that of a point on the slanted face the last three
+// (distance t = -(di + dj + dk) = 0, 1, 2 from the face).  Those three
+// values of every row are staged once in LDS, the first from S0 or S1
+// (contiguous over j) and the other two from the head or tail of the row's M
+// run (two neighbouring lanes per row, one cache line), and every point then
+// reads its stencil from LDS.  Rows are split by the parity of j so that the
+// lanes of a wave (every other row) read consecutive LDS words.
+enum { kFaceStage = kP2FaceRows + 4, kFaceHalf = kFaceStage / 2,
+       kFacePlanes = kP2FaceK + 4 };
+
+template <typename T>
+struct FaceImage {
+  T v[kFacePlanes][3][2][kFaceHalf];  // [plane k0 - 2 + p][t][j parity][row / 2]
+};
+
+// Offset of point (i, j, k) with 0 <= i <= e = n - j - k.
+__device__ __forceinline__ int32_t face_slot(const Lay& L, int i, int j, int k) {
+  const int n = L.n, e = n - j - k;
+  const int32_t s0 = (int32_t)L.off_s0 + t2w32(n + 1, j, k);
+  const int32_t s1 = (int32_t)L.off_s1 + t2w32(n, j, k);
+  const int32_t m = tw32(n - 1, i - 1, j, k);
+  return i == 0 ? s0 : (i == e ? s1 : m);
+}
+
+template <typename T, int P, int SIDE>
+__device__ __forceinline__ void p2_face_tile_points(const P2Args& a, const FaceImage<T>& im,
+                                                    int64_t cell, int q, int k, int jb,
+                                                    int lane) {
+  constexpr int S = (P >> 1) & 1;  // parity of j (jb is even)
+  const int n = a.n;
+  const int j = jb + S + 2 * lane;
+  const bool valid = j >= 1 && j <= n - k - 1;
+  const int cls = (SIDE == 0 ? 1 : 8) | ((k == 0) << 2);
+  typedef const __attribute__((address_space(4))) T* wptr;
+  const wptr wp = (wptr)((const T*)a.w + cell * (int64_t)kP2PerCell) +
+                  (P * kNumClasses + cls) * kP2MaxOffsets;
+  T acc = 0;
+  static_for<kP2Off.len[P]>([&](auto TT) {
+    constexpr int t = decltype(TT)::value;
+    constexpr int di = kP2Off.d[P][t][0], dj = kP2Off.d[P][t][1], dk = kP2Off.d[P][t][2];
+    static_assert(di >= -2 && di <= 2 && dj >= -2 && dj <= 2 && dk >= -2 && dk <= 2 &&
+                      di + dj + dk >= -2 && di + dj + dk <= 2,
+                  "P2 stencil reaches two points in every direction");
+    if constexpr ((SIDE == 0 && di >= 0) || (SIDE == 1 && di + dj + dk <= 0)) {
+      constexpr int tt = SIDE == 0 ? di : -(di + dj + dk);
+      // staged row j + dj is row index j - jb + 2 + dj = S + 2 + dj + 2 lane
+      constexpr int r = S + 2 + dj;
+      acc += wp[t] * im.v[q + 2 + dk][tt][r & 1][(r >> 1) + lane];
+    }
+  });
+  const int64_t bytes = a.stride * (int64_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc((T*)a.y + cell * a.stride, bytes);
+  const int el = SIDE == 0 ? (int)a.off_s0 + t2w32(n + 1, j, k) : (int)a.off_s1 + t2w32(n, j, k);
+  bstore(acc, ry, valid ? (unsigned)el * (unsigned)sizeof(T) : HT_OOB);
+}
+
+template <typename T, int SIDE>
+__device__ __forceinline__ void p2_face_tile_task(const P2Args& a, const FaceImage<T>& im,
+                                                  int64_t cell, int q, int k, int jb,
+                                                  int lane, int P) {
+  switch (P) {
+    case 0: p2_face_tile_points<T, 0, SIDE>(a, im, cell, q, k, jb, lane); break;
+    case 1: p2_face_tile_points<T, 1, SIDE>(a, im, cell, q, k, jb, lane); break;
+    case 2: p2_face_tile_points<T, 2, SIDE>(a, im, cell, q, k, jb, lane); break;
+    case 3: p2_face_tile_points<T, 3, SIDE>(a, im, cell, q, k, jb, lane); break;
+    case 4: p2_face_tile_points<T, 4, SIDE>(a, im, cell, q, k, jb, lane); break;
+    case 5: p2_face_tile_points<T, 5, SIDE>(a, im, cell, q, k, jb, lane); break;
+    case 6: p2_face_tile_points<T, 6, SIDE>(a, im, cell, q, k, jb, lane); break;
+    default: p2_face_tile_points<T, 7, SIDE>(a, im, cell, q, k, jb, lane); break;
+  }
+}
+
+// One workgroup per face tile (make_p2_face_tiles).
+template <typename T>
+__global__ __launch_bounds__(256) void k_p2_face(P2Args a) {
+  __shared__ FaceImage<T> im;
+  const int64_t wb = xcd_block(a.nc * a.nftiles);
+  if (wb >= a.nc * a.nftiles) return;
+  const int64_t cell = wb / a.nftiles;
+  const int2 tl = a.ftiles[wb % a.nftiles];
+  const int k0 = tl.x & 0xffff, side = (tl.x >> 16) & 1, jb = tl.y;
+  const int n = a.n;
+  const Lay L{n, a.stride, a.off_s0, a.off_s1};
+  const int64_t bytes = a.stride * (int64_t)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
+  // t = 0: the face point of every staged row (S0 on face i = 0; S1 on the
+  // slanted face, S0 for a one-point row)
+  for (int e = threadIdx.x; e < kFacePlanes * kFaceStage; e += 256) {
+    const int p = e / kFaceStage, r = e - p * kFaceStage;
+    const int kk = k0 - 2 + p, jj = jb - 2 + r, ee = n - jj - kk;
+    const bool ok = kk >= 0 && jj >= 0 && ee >= 0;
+    const int i = side == 0 ? 0 : ee;
+    T v;
+    bload(v, rx, ok ? (unsigned)face_slot(L, i, jj, kk) * (unsigned)sizeof(T) : HT_OOB);
+    im.v[p][0][r & 1][r >> 1] = v;
+  }
+  // t = 1, 2: two neighbouring lanes per row
+  for (int e = threadIdx.x; e < 2 * kFacePlanes * kFaceStage; e += 256) {
+    const int pr = e >> 1, t = 1 + (e & 1);
+    const int p = pr / kFaceStage, r = pr - p * kFaceStage;
+    const int kk = k0 - 2 + p, jj = jb - 2 + r, ee = n - jj - kk;
+    const bool ok = kk >= 0 && jj >= 0 && t <= ee;
+    const int i = side == 0 ? t : ee - t;
+    T v;
+    bload(v, rx, ok ? (unsigned)face_slot(L, i, jj, kk) * (unsigned)sizeof(T) : HT_OOB);
+    im.v[p][t][r & 1][r >> 1] = v;
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = (int)(threadIdx.x & 63);
+  for (int task = wave; task < 2 * kP2FaceK; task += 4) {
+    const int q = task >> 1, sj = task & 1, k = k0 + q;
+    if (k > n - 2) break;  // no rows 1 <= j <= n - k - 1 from here on
+    const int sk = k & 1;
+    if (side == 0) p2_face_tile_task<T, 0>(a, im, cell, q, k, jb, lane, (sj << 1) | (sk << 2));
+    else p2_face_tile_task<T, 1>(a, im, cell, q, k, jb, lane,
+                                 ((sj + sk) & 1) | (sj << 1) | (sk << 2));
   }
 }
 
@@ -275,14 +392,18 @@ void launch_p2_t(int J, const P2Args& a, hipStream_t s) {
   const int64_t nb = a.nc * a.nblk, nf = a.nc * a.nfblk;
   if (nb > 0) {
     const dim3 grid((unsigned)(((nb + 7) / 8) * 8));
-    switch (J) {
-      case 2: hipLaunchKernelGGL((k_p2_march<T, 2>), grid, block, 0, s, a); break;
-      case 4: hipLaunchKernelGGL((k_p2_march<T, 4>), grid, block, 0, s, a); break;
-      default: throw Error{HT_ERR_ARG, "P2 tile rows must be 2 or 4"};
-    }
+    // rows per march column: 2 in FP64 (register ring of 127 VGPRs), 4 in FP32
+    constexpr int JT = sizeof(T) == 8 ? 2 : 4;
+    if (J != JT) throw Error{HT_ERR_ARG, "P2 tile rows must be 2 in FP64 and 4 in FP32"};
+    hipLaunchKernelGGL((k_p2_march<T, JT>), grid, block, 0, s, a);
   }
   if (nf > 0) {
     const dim3 grid((unsigned)(((nf + 7) / 8) * 8));
+    hipLaunchKernelGGL((k_p2_edge<T>), grid, block, 0, s, a);
+  }
+  const int64_t nt = a.nc * a.nftiles;
+  if (nt > 0) {
+    const dim3 grid((unsigned)(((nt + 7) / 8) * 8));
     hipLaunchKernelGGL((k_p2_face<T>), grid, block, 0, s, a);
   }
 }

@@ -114,23 +114,29 @@ enum { kP2PerCell = kP2Parities * kNumClasses * kP2MaxOffsets };
 void p2_cell_weights(const double X[4][3], double* w /* [kP2PerCell] */);
 
 // Work of one cell for the bulk kernel: k-march segments (j0 | k0 << 16, i0)
-// of J rows x 124 points from plane k0; for the face kernel: runs (k | side << 16 | s << 17, j0) of the
-// 64 points j = j0 + 2 lane + s of face i = 0 (side 0) or i = n - j - k
-// (side 1) in plane k.
+// of J rows x 124 points from plane k0.  Face points of the rows
+// 1 <= j <= n - k - 1 (one boundary class per plane and face): face tiles
+// (k0 | side << 16, jb) of kP2FaceK planes from k0 and the kP2FaceRows rows
+// from jb, on face i = 0 (side 0) or i = n - j - k (side 1).  Face points on
+// the edges j = 0 and (face i = 0) j = n - k, whose class varies along the
+// edge: edge runs (side << 16 | s << 17 | edge << 19, k0) of the 64 points
+// k = k0 + 2 lane + s of the edge j = 0 (edge 0) or j = n - k (edge 1).
 struct P2Args {
   const void* x;
   void* y;
   const void* w;          // [nc][kP2PerCell] level-scaled weights
   const int2* tiles;      // k-march segments of one cell
   int64_t ntiles, nblk;   // tiles per cell, blocks per cell
-  const int2* runs;       // face runs of one cell
+  const int2* ftiles;     // face tiles of one cell
+  int64_t nftiles;
+  const int2* runs;       // edge runs of one cell
   int64_t nruns, nfblk;
   int64_t nc;
   int64_t stride, off_s0, off_s1;
   int n;                  // fine intervals per macro-edge, 2^(l+1)
   int kseg;               // planes per k-march segment (a multiple of 10)
 };
-enum { kP2TileI = 124 };
+enum { kP2TileI = 124, kP2FaceK = 8, kP2FaceRows = 128 };
 
 void launch_p2(int dtype, int J, const P2Args& a, hipStream_t s);
 
