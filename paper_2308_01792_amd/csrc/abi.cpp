@@ -345,7 +345,7 @@ struct Shape {
 // operations the band kernel runs
 static bool band_op(int op) {
   return op == OP_APPLY || op == OP_JACOBI || op == OP_RESID || op == OP_RESID32 ||
-         op == OP_RESID32X;
+         op == OP_RESID32X || op == OP_JACOBIADD;
 }
 // untuned sweeps use the band kernel from this level on (measured at level 8:
 // Jacobi 4.22 against 4.94 ms in FP64, 2.49 against 2.78 ms in FP32); below,
@@ -353,11 +353,18 @@ static bool band_op(int op) {
 static const int kBandSweepLevel = 7;
 static Shape choose_shape(ht_mesh* h, int level, int dtype, int op) {
   if (op == OP_APPLY) return Shape{choose_J(h, level, dtype), false, march_segment(false)};
+  const bool in_i = (1 << level) >= 62 * (kCellWaves - 1) + 1;
+  // the sweep that adds its result to an FP64 iterate exists on the band
+  // kernel only; it replaces a sweep plus a separate update pass, so it runs
+  // there whatever shape the other sweeps take
+  if (op == OP_JACOBIADD)
+    return (level >= kBandSweepLevel && has_band(h, level, dtype))
+               ? Shape{0, in_i, march_segment(in_i)}
+               : Shape{kDefaultJ, in_i, march_segment(in_i)};
   if (!op_is_sweep(op)) {
     const int J = choose_J(h, level, dtype);
     return Shape{J == 0 ? kDefaultJ : J, false, march_segment(false)};
   }
-  const bool in_i = (1 << level) >= 62 * (kCellWaves - 1) + 1;
   auto it = h->tuned_sweep.find({level, dtype});
   if (it != h->tuned_sweep.end()) {
     // the band kernel (J = 0) runs the Jacobi sweep and the residual; the
@@ -472,10 +479,12 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
 // wave plus one per exchange block.
 static int64_t pass_partials(ht_mesh* h, int level, int dtype, int op, const Range& R);
 
-// Extra output of the fused refinement pass (OP_RESID32X): the first
-// zero-guess sweep of the next correction.
+// Extra output of the fused refinement passes: the first zero-guess sweep
+// of the next correction (OP_RESID32X), the FP64 iterate that the last sweep
+// of a correction is added to (OP_JACOBIADD).
 struct Fuse {
   void* efirst = nullptr;
+  double* uadd = nullptr;
 };
 
 static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
@@ -492,17 +501,19 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
     BandArgs ba = band_args(h, level, dtype, x, y, R, b, omega, partials);
     ba.y32 = (float*)at_cell(y32, R.c0, level, HT_F32);
     if (fuse) ba.efirst = (float*)at_cell(fuse->efirst, R.c0, level, HT_F32);
+    if (fuse) ba.uadd = (double*)at_cell(fuse->uadd, R.c0, level, HT_F64);
     const bool res = op == OP_RESID || op == OP_RESID32 || op == OP_RESID32X;
     {
       Prof p(h, op == OP_APPLY ? "cell_apply" : res ? "cell_residual" : "cell_jacobi", s);
       launch_band(dtype, op, ba, s);
       check_launch();
     }
-    ExchArgs ea = exch_args(h, level, y, op == OP_JACOBI ? x : nullptr, b, omega,
-                            partials + kBandComputeWaves * ba.nblocks, R);
+    ExchArgs ea = exch_args(h, level, y, (op == OP_JACOBI || op == OP_JACOBIADD) ? x : nullptr,
+                            b, omega, partials + kBandComputeWaves * ba.nblocks, R);
     if (res) ea.u = x;
     ea.y32 = y32;
     if (fuse) ea.efirst = fuse->efirst;
+    if (fuse) ea.uadd = fuse->uadd;
     if (ea.total > 0) {
       Prof p(h, "exchange", s);
       launch_exchange(dtype, op, ea, s);
@@ -516,6 +527,8 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
     }
     return;
   }
+  if (op == OP_JACOBIADD)
+    throw Error{HT_ERR_STATE, "the sweep added to the iterate runs on the band kernel only"};
   CellArgs ca = cell_args(h, level, dtype, sh, x, y, b, omega, R);
   ca.y32 = at_cell(y32, R.c0, level, HT_F32);
   ca.partials = partials;
@@ -984,13 +997,23 @@ static void* smooth(ht_mesh* h, int level, int dtype, const ht_cycle_opts& o,
 static double norm_of(ht_mesh* h, int level, int dtype, const void* a,
                       const void* b, hipStream_t s, bool sq);
 
+// Whether the last sweep of an FP32 correction on `level` can add its result
+// to an FP64 iterate (OP_JACOBIADD runs on the band kernel).
+static bool can_add_last_sweep(ht_mesh* h, int level, const ht_cycle_opts& o) {
+  return o.smoother == HT_SMOOTH_JACOBI && o.nu2 > 0 && level > o.coarse_level &&
+         choose_shape(h, level, HT_F32, OP_JACOBIADD).J == 0;
+}
+
 // V(nu1, nu2) on `level`: iterate in u (or t), returns the buffer with the
 // new iterate.  zero_guess: the incoming iterate is zero.  first_done: the
-// first pre-smoothing sweep has already been made from u into t.
+// first pre-smoothing sweep has already been made from u into t.  uadd (FP32
+// cycles where can_add_last_sweep holds): the last post-smoothing sweep adds
+// its result to this FP64 vector instead of storing it; the returned buffer
+// is then the one that sweep would have written, and holds scratch.
 static void* vcycle_impl(ht_mesh* h, int level, int dtype,
                          const ht_cycle_opts& o, void* u, void* t,
                          const void* b, bool zero_guess, hipStream_t s,
-                         bool first_done = false) {
+                         bool first_done = false, double* uadd = nullptr) {
   if (level == o.coarse_level) {
     coarse_fast(h, level, dtype, b, u, s);
     return u;
@@ -1013,7 +1036,16 @@ static void* vcycle_impl(ht_mesh* h, int level, int dtype,
   restrict_pass(h, level, dtype, other, wc.b, s, full_range(h->m));
   void* ec = vcycle_impl(h, level - 1, dtype, o, wc.u, wc.t, wc.b, true, s);
   prolong_pass(h, level - 1, dtype, ec, cur, s, full_range(h->m));
-  return smooth(h, level, dtype, o, o.nu2, cur, other, b, s);
+  if (!uadd) return smooth(h, level, dtype, o, o.nu2, cur, other, b, s);
+  if (dtype != HT_F32 || !can_add_last_sweep(h, level, o))
+    throw Error{HT_ERR_STATE, "the last sweep cannot be added to the iterate here"};
+  cur = smooth(h, level, dtype, o, o.nu2 - 1, cur, other, b, s);
+  other = (cur == u) ? t : u;
+  Fuse F;
+  F.uadd = uadd;
+  op_pass(h, level, dtype, OP_JACOBIADD, cur, other, b, o.omega, s, false, 0,
+          full_range(h->m), nullptr, nullptr, nullptr, &F);
+  return other;
 }
 
 static void check_cycle(const Mesh& m, int level, const ht_cycle_opts* o) {
@@ -1797,6 +1829,8 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
     // the V-cycle started from a done first sweep in its t buffer ends in t
     // after an even number of further sweeps
     const bool e_in_t = ((o->cyc.nu1 - 1 + o->cyc.nu2) % 2) == 0;
+    // the last sweep of each correction adds its result to u (no update pass)
+    double* uadd = mixed && can_add_last_sweep(h, level, o->cyc) ? (double*)u : nullptr;
     // residual of the initial iterate (mixed: delivered in FP32 as the
     // right-hand side of the first correction)
     if (fused) {
@@ -1834,10 +1868,10 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
       }
       if (fused) {
         void* e = vcycle_impl(h, level, HT_F32, o->cyc, fother, ffirst, w32->b, false,
-                              ss, true);
+                              ss, true, uadd);
         if (e != (e_in_t ? ffirst : fother))
           throw Error{HT_ERR_STATE, "refinement: correction not in the expected buffer"};
-        flat(h, level, HT_F64, HT_F32, FOP_ADD, u, e, ss);
+        if (!uadd) flat(h, level, HT_F64, HT_F32, FOP_ADD, u, e, ss);
         Fuse F;
         F.efirst = e == w32->u ? w32->t : w32->u;
         op_pass(h, level, HT_F64, OP_RESID32X, u, w64.t, b, o->cyc.omega, ss, true, 0,
@@ -1848,8 +1882,9 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
       } else {
         // FP32 correction of the FP64 residual (rounded to FP32 in w32->b),
         // FP64 update, FP64 residual of the new iterate rounded to FP32
-        void* e = vcycle_impl(h, level, HT_F32, o->cyc, w32->u, w32->t, w32->b, true, ss);
-        flat(h, level, HT_F64, HT_F32, FOP_ADD, u, e, ss);
+        void* e = vcycle_impl(h, level, HT_F32, o->cyc, w32->u, w32->t, w32->b, true, ss,
+                              false, uadd);
+        if (!uadd) flat(h, level, HT_F64, HT_F32, FOP_ADD, u, e, ss);
         op_pass(h, level, HT_F64, OP_RESID32, u, w64.t, b, 0.0, ss, true, 0,
                 full_range(h->m), w32->b);
       }
@@ -2393,38 +2428,48 @@ static void autotune_level(ht_mesh* h, int level, int dtype, const char* cache_p
       HT_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
       return ms;
     };
+    // Every candidate is timed in two rounds and keeps its faster time, so
+    // that a clock ramp or a noisy first launch does not decide the choice.
+    HT_CHECK_HIP(hipMemsetAsync(x, 0, bytes, s));
+    HT_CHECK_HIP(hipMemsetAsync(y, 0, bytes, s));
+    HT_CHECK_HIP(hipMemsetAsync(bv, 0, bytes, s));
+    const int kRounds = 2;
     // apply: the band kernel, or the tile kernel with J rows per wave and
     // the waves stacked in j
-    float best_ms = 1e30f;
     std::vector<int> cand(std::begin(kJ), std::end(kJ));
     if (has_band(h, level, dtype)) cand.insert(cand.begin(), 0);
-    for (int J : cand) {
-      h->tuned_J[{level, dtype}] = J;
-      const float ms = time_of([&] { op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s, false, 0, R); });
-      if (ms < best_ms) { best_ms = ms; best = J; }
-    }
+    std::vector<float> ms_apply(cand.size(), 1e30f);
+    for (int round = 0; round < kRounds; ++round)
+      for (size_t c = 0; c < cand.size(); ++c) {
+        h->tuned_J[{level, dtype}] = cand[c];
+        const float ms = time_of([&] { op_pass(h, level, dtype, OP_APPLY, x, y, nullptr, 0.0, s, false, 0, R); });
+        ms_apply[c] = std::min(ms_apply[c], ms);
+      }
+    best = cand[std::min_element(ms_apply.begin(), ms_apply.end()) - ms_apply.begin()];
     h->tuned_J[{level, dtype}] = best;
     // sweeps: the band kernel, or the tile kernel's rows per wave, wave
     // arrangement and march segment length, on the Jacobi sweep with its
     // own right-hand side (b streams from HBM as in a solve)
-    best_ms = 1e30f;
+    std::vector<SweepShape> scand;
     if (has_band(h, level, dtype)) {
       const bool in_i = (1 << level) >= 62 * (kCellWaves - 1) + 1;
-      h->tuned_sweep[{level, dtype}] = {0, in_i, march_segment(in_i)};
-      const float ms = time_of(
-          [&] { op_pass(h, level, dtype, OP_JACOBI, x, y, bv, 2.0 / 3.0, s, false, 0, R); });
-      best_ms = ms;
-      best_sweep = {0, in_i, march_segment(in_i)};
+      scand.push_back({0, in_i, march_segment(in_i)});
     }
     for (int J : kJ)
       for (bool in_i : {false, true})
         for (int sg : kSegs) {
           seg_tiles(h, level, J, in_i, sg);
-          h->tuned_sweep[{level, dtype}] = {J, in_i, sg};
-          const float ms = time_of(
-              [&] { op_pass(h, level, dtype, OP_JACOBI, x, y, bv, 2.0 / 3.0, s, false, 0, R); });
-          if (ms < best_ms) { best_ms = ms; best_sweep = {J, in_i, sg}; }
+          scand.push_back({J, in_i, sg});
         }
+    std::vector<float> ms_sweep(scand.size(), 1e30f);
+    for (int round = 0; round < kRounds; ++round)
+      for (size_t c = 0; c < scand.size(); ++c) {
+        h->tuned_sweep[{level, dtype}] = scand[c];
+        const float ms = time_of(
+            [&] { op_pass(h, level, dtype, OP_JACOBI, x, y, bv, 2.0 / 3.0, s, false, 0, R); });
+        ms_sweep[c] = std::min(ms_sweep[c], ms);
+      }
+    best_sweep = scand[std::min_element(ms_sweep.begin(), ms_sweep.end()) - ms_sweep.begin()];
   } catch (...) {
     h->tuned_sweep.erase({level, dtype});
     release();

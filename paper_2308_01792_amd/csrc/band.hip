@@ -232,7 +232,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
   // ------------------------------------------------------ compute waves --
   const __amdgpu_buffer_rsrc_t ry = make_rsrc((T*)a.y + cell * a.stride, bytes);
   constexpr bool R32 = OP == OP_RESID32 || OP == OP_RESID32X;
-  constexpr bool SWEEP = OP == OP_JACOBI || OP == OP_RESID || R32;
+  constexpr bool ADD = OP == OP_JACOBIADD;
+  constexpr bool SWEEP = OP == OP_JACOBI || OP == OP_RESID || R32 || ADD;
   const __amdgpu_buffer_rsrc_t ry32 =
       make_rsrc(R32 ? a.y32 + cell * a.stride : (float*)a.y, R32 ? a.stride * 4 : 0);
   const __amdgpu_buffer_rsrc_t ref =
@@ -240,6 +241,9 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
                 OP == OP_RESID32X ? a.stride * 4 : 0);
   const __amdgpu_buffer_rsrc_t rb =
       make_rsrc(SWEEP ? (const T*)a.b + cell * a.stride : (const T*)a.x, SWEEP ? bytes : 0);
+  // OP_JACOBIADD: the FP64 iterate (byte offset of a point = 2 x its FP32 one)
+  const __amdgpu_buffer_rsrc_t ru =
+      make_rsrc(ADD ? a.uadd + cell * a.stride : (double*)a.y, ADD ? a.stride * 8 : 0);
   // omega D^-1 at the cell's interior points (as the tile kernel forms it)
   const T omega_invd = SWEEP ? (T)(a.omega * a.nscale * a.cls[cell * 16].inv_diag_unit) : (T)0;
   double nsq = 0.0;  // |r|^2 of the points this wave finishes
@@ -337,6 +341,12 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
         bv1 = __builtin_amdgcn_raw_buffer_load_b128(rb, (st1a || st1b) ? e1 : HT_OOB, 0, 0);
         bv2 = __builtin_amdgcn_raw_buffer_load_b128(rb, (st2a || st2b) ? e2 : HT_OOB, 0, 0);
       }
+      // OP_JACOBIADD: u at the four points (two FP64 pairs)
+      u32x4 uv1 = {0u, 0u, 0u, 0u}, uv2 = {0u, 0u, 0u, 0u};
+      if constexpr (ADD) {
+        uv1 = __builtin_amdgcn_raw_buffer_load_b128(ru, (st1a || st1b) ? 2 * e1 : HT_OOB, 0, 0);
+        uv2 = __builtin_amdgcn_raw_buffer_load_b128(ru, (st2a || st2b) ? 2 * e2 : HT_OOB, 0, 0);
+      }
       // ten rows (dj, dk) at columns A, A + 1: plane k rows r - 1 .. r + 2,
       // plane k + 1 rows r - 1 .. r + 1, plane k - 1 rows r .. r + 2
       const int q0 = sk + A, q1 = q0 + v, q2 = q1 + v - 1, qm = q0 - v - 1;
@@ -375,7 +385,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
             if constexpr (OP == OP_RESID32X) bstore((float)omega_invd * (float)rr, ref, f);
             return acc;
           }
-          return surf ? acc : (OP == OP_JACOBI ? fma(omega_invd, rr, xc) : rr);
+          return surf ? acc : ((OP == OP_JACOBI || ADD) ? fma(omega_invd, rr, xc) : rr);
         };
         a1 = fin(a1, K0.a, b1v[0], st1a, surf1, e1);
         b1 = fin(b1, K0.b, b1v[1], st1b, surf1, e1 + sz);
@@ -383,6 +393,22 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_band(BandArgs a) {
         b2 = fin(b2, K1.b, b2v[1], st2b, surf2, e2 + sz);
         if constexpr (R32) {
           // only the face points keep an FP64 partial row
+          if constexpr (SPECIAL) {
+            bstore(a1, ry, st1a && surf1 ? e1 : HT_OOB);
+            bstore(b1, ry, st1b && surf1 ? e1 + sz : HT_OOB);
+            bstore(a2, ry, st2a && surf2 ? e2 : HT_OOB);
+            bstore(b2, ry, st2b && surf2 ? e2 + sz : HT_OOB);
+          }
+          return;
+        }
+        if constexpr (ADD) {
+          // finished points: u += e_new in FP64; face points: partial rows
+          const double* u1 = reinterpret_cast<const double*>(&uv1);
+          const double* u2 = reinterpret_cast<const double*>(&uv2);
+          bstore(u1[0] + (double)a1, ru, st1a && !surf1 ? 2 * e1 : HT_OOB);
+          bstore(u1[1] + (double)b1, ru, st1b && !surf1 ? 2 * (e1 + sz) : HT_OOB);
+          bstore(u2[0] + (double)a2, ru, st2a && !surf2 ? 2 * e2 : HT_OOB);
+          bstore(u2[1] + (double)b2, ru, st2b && !surf2 ? 2 * (e2 + sz) : HT_OOB);
           if constexpr (SPECIAL) {
             bstore(a1, ry, st1a && surf1 ? e1 : HT_OOB);
             bstore(b1, ry, st1b && surf1 ? e1 + sz : HT_OOB);
@@ -464,6 +490,12 @@ static void launch_band_t(int op, const BandArgs& a, hipStream_t s) {
     case OP_RESID:
       hipLaunchKernelGGL((k_band<T, OP_RESID>), grid, dim3(kBandThreads), 0, s, a);
       break;
+    case OP_JACOBIADD:
+      if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((k_band<T, OP_JACOBIADD>), grid, dim3(kBandThreads), 0, s, a);
+        break;
+      }
+      throw Error{HT_ERR_ARG, "band kernel: the sweep added to u is an FP32 operation"};
     case OP_RESID32:
     case OP_RESID32X:
       if constexpr (sizeof(T) == 8) {

@@ -188,6 +188,9 @@ struct BandArgs {
   // for OP_RESID32X the next correction's first Jacobi sweep omega D^-1 r
   float* y32;
   float* efirst;
+  // the last sweep of an FP32 correction (OP_JACOBIADD): u += e_new in FP64
+  // at the finished points (y holds the partial rows of the others)
+  double* uadd;
   int64_t nitems, nblocks;
   int64_t stride, off_s0, off_s1;
   int n;

@@ -473,11 +473,12 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       }
       T val;
       if (P.boundary) {
-        val = (OP == OP_JACOBI || OP == OP_CHEB) ? ((const T*)a.u)[s0] : (T)0;
+        val = (OP == OP_JACOBI || OP == OP_JACOBIADD || OP == OP_CHEB) ? ((const T*)a.u)[s0]
+                                                                      : (T)0;
       } else if (OP == OP_RESID || OP == OP_RESID32 || OP == OP_RESID32X) {
         val = ((const T*)a.b)[s0] - sum;
         nsq = (double)val * (double)val;
-      } else if (OP == OP_JACOBI) {
+      } else if (OP == OP_JACOBI || OP == OP_JACOBIADD) {
         const T invd = (T)(a.nscale * P.inv_diag_unit);
         const T r = ((const T*)a.b)[s0] - sum;
         nsq = (double)r * (double)r;
@@ -507,6 +508,10 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
           ef[s0] = e;
           for (int q = 1; q < cnt; ++q) ef[slot_q(q)] = e;
         }
+      } else if (OP == OP_JACOBIADD) {
+        double* ua = a.uadd;
+        ua[s0] += (double)val;
+        for (int q = 1; q < cnt; ++q) ua[slot_q(q)] += (double)val;
       } else {
         y[s0] = val;
         for (int q = 1; q < cnt; ++q) y[slot_q(q)] = val;
@@ -514,7 +519,7 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
     }
   }
   if (OP == OP_RESID || OP == OP_JACOBI || OP == OP_RESID32 || OP == OP_CHEB ||
-      OP == OP_RESID32X) {
+      OP == OP_RESID32X || OP == OP_JACOBIADD) {
     __shared__ double red[4];
     nsq = wave_sum(nsq);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nsq;
@@ -643,17 +648,21 @@ static void launch_exchange_t(int op, const ExchArgs& a, hipStream_t s) {
     case OP_RESID32: hipLaunchKernelGGL((k_exchange<T, OP_RESID32>), grid, dim3(256), 0, s, a); break;
     case OP_RESID32X: hipLaunchKernelGGL((k_exchange<T, OP_RESID32X>), grid, dim3(256), 0, s, a); break;
     case OP_CHEB: hipLaunchKernelGGL((k_exchange<T, OP_CHEB>), grid, dim3(256), 0, s, a); break;
+    case OP_JACOBIADD:
+      if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_exchange<T, OP_JACOBIADD>), grid, dim3(256), 0, s, a);
+      break;
   }
 }
 void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
   if (a.total <= 0) return;
   if (op != OP_APPLY && op != OP_RESID && op != OP_JACOBI && op != OP_SYNC &&
       op != OP_FILL && op != OP_RESTRICT && op != OP_RESID32 && op != OP_CHEB &&
-      op != OP_RESID32X)
+      op != OP_RESID32X && op != OP_JACOBIADD)
     throw Error{HT_ERR_ARG, "unknown exchange operation"};
   // the residual and Jacobi epilogues read u and b at the owner copy
   if ((op == OP_RESID || op == OP_JACOBI || op == OP_RESID32 || op == OP_CHEB ||
-       op == OP_RESID32X) &&
+       op == OP_RESID32X || op == OP_JACOBIADD) &&
       (!a.u || !a.b))
     throw Error{HT_ERR_ARG, "exchange for residual/Jacobi needs u and b"};
   if (op == OP_CHEB && !a.d) throw Error{HT_ERR_ARG, "Chebyshev step needs d"};
@@ -661,6 +670,8 @@ void launch_exchange(int dtype, int op, const ExchArgs& a, hipStream_t s) {
     throw Error{HT_ERR_ARG, "FP32 residual output needs FP64 input and y32"};
   if (op == OP_RESID32X && !a.efirst)
     throw Error{HT_ERR_ARG, "fused refinement pass needs the first-sweep output"};
+  if (op == OP_JACOBIADD && (dtype != HT_F32 || !a.uadd))
+    throw Error{HT_ERR_ARG, "the sweep added to the iterate is an FP32 sweep into FP64 u"};
   if (dtype == HT_F64) launch_exchange_t<double>(op, a, s);
   else launch_exchange_t<float>(op, a, s);
 }

@@ -16,8 +16,13 @@ namespace ht {
 // OP_RESID32X: OP_RESID32 plus the first zero-guess Jacobi sweep
 // omega D^-1 r of the next FP32 correction (efirst), so that iterative
 // refinement needs no separate pass for that sweep.
+// OP_JACOBIADD: the last Jacobi sweep of an FP32 correction e, whose result
+// is not stored but added to the FP64 iterate (u += e_new at every slot), so
+// that iterative refinement needs no separate update pass (band kernel,
+// FP32 only).
 enum { OP_APPLY = 0, OP_RESID = 1, OP_JACOBI = 2, OP_SYNC = 3, OP_FILL = 4,
-       OP_RESTRICT = 5, OP_RESID32 = 6, OP_CHEB = 7, OP_RESID32X = 8 };
+       OP_RESTRICT = 5, OP_RESID32 = 6, OP_CHEB = 7, OP_RESID32X = 8,
+       OP_JACOBIADD = 9 };
 enum { EOP_ZERO_GUESS = 0, EOP_MASS = 1, EOP_ZERO_INTERIOR = 2, EOP_DOT = 3,
        EOP_FLAGS = 4, EOP_COORDS = 5, EOP_PROBE = 6 };
 enum { FOP_COPY = 0, FOP_ADD = 1, FOP_ZERO = 2 };
@@ -33,7 +38,7 @@ enum { kCellWaves = HT_CELL_WAVES };
 // apply's.
 constexpr bool op_is_sweep(int op) {
   return op == OP_RESID || op == OP_JACOBI || op == OP_RESID32 || op == OP_CHEB ||
-         op == OP_RESID32X;
+         op == OP_RESID32X || op == OP_JACOBIADD;
 }
 
 struct CellArgs {
@@ -64,6 +69,7 @@ struct ExchArgs {
   void* y;
   void* y32;            // FP32 residual (OP_RESID32, OP_RESID32X)
   void* efirst;         // OP_RESID32X: omega D^-1 r in FP32
+  double* uadd;         // OP_JACOBIADD: FP64 iterate that receives the sweep
   void* d;              // Chebyshev direction (OP_CHEB)
   double c1, c2;
   const void* u;

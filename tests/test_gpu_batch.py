@@ -199,3 +199,23 @@ def test_autotuned_batch_matches_individual_solves():
         for (ur, sr), u, s in zip(ref, us, st):
             assert s["cycles"] == sr["cycles"]
             assert rel_err(u.cpu().numpy(), ur.cpu().numpy()) <= 1e-12
+
+
+def test_mixed_update_inside_the_last_sweep_matches_a_separate_update():
+    """From level 7 on, a single mixed solve adds each FP32 correction to u
+    inside its last post-smoothing sweep (band kernel); the batch path keeps
+    the separate update pass.  Three refinement steps of one jittered box at
+    level 7 give the same iterate both ways."""
+    from workloads import jittered_kuhn_box
+    L = 7
+    m = ht.Mesh(*jittered_kuhn_box(2, 1, 1, amplitude=0.1, seed=4), 2, L)
+    b = _rhs(m, L, 77)
+    kw = dict(rel_tol=0.0, max_cycles=3, raise_on_fail=False)
+    u1 = torch.zeros_like(b)
+    s1 = m.solve(L, u1, b, ht.HT_PREC_MIXED, **kw)
+    batch = ht.Batch([m], [L])
+    u2 = torch.zeros_like(b)
+    s2 = batch.solve([u2], [b], precision=ht.HT_PREC_MIXED, **kw)[0]
+    assert s1["cycles"] == s2["cycles"] == 3
+    assert np.allclose(s1["history"], s2["history"], rtol=1e-12, atol=0)
+    assert rel_err(u1.cpu().numpy(), u2.cpu().numpy()) <= 1e-13
