@@ -684,12 +684,16 @@ static const void* p2_weights(ht_mesh* h, int level, int dtype) {
 // j0 .. j0 + J - 1, points i0 + 2 .. i0 + 125 and planes k0 .. k0 + seg - 1
 // up to the last plane where row j0 has a point 1 <= i <= e - 1.
 static std::vector<int2> make_p2_columns(int n, int J, int seg) {
+  // segment-major: the waves of a workgroup, and neighbouring workgroups,
+  // march the same planes over neighbouring rows and share their halo rows
+  // in cache
   std::vector<int2> t;
-  for (int j0 = 0; n - j0 >= 2; j0 += J)
-    for (int i0 = -2; i0 + 2 <= n - j0 - 1; i0 += kP2TileI) {
-      const int kcol = n - j0 - std::max(2, i0 + 3);
-      for (int k0 = 0; k0 <= kcol; k0 += seg) t.push_back(make_int2(j0 | (k0 << 16), i0));
-    }
+  for (int k0 = 0; k0 <= n - 2; k0 += seg)
+    for (int j0 = 0; n - j0 >= 2; j0 += J)
+      for (int i0 = -2; i0 + 2 <= n - j0 - 1; i0 += kP2TileI) {
+        const int kcol = n - j0 - std::max(2, i0 + 3);
+        if (k0 <= kcol) t.push_back(make_int2(j0 | (k0 << 16), i0));
+      }
   return t;
 }
 // Face work of one cell (faces i = 0, side 0, and i = n - j - k, side 1):
