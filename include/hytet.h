@@ -107,6 +107,10 @@ typedef struct {
   double rel_res;      /* final relative residual (FP64) */
   double seconds;      /* wall time of the solve */
   double res_history[257]; /* relative residual before cycle 0, 1, ... */
+  int stagnated;       /* 1: stopped because three cycles in a row brought no
+                          new minimum of the residual (rounding floor of the
+                          precision reached above rel_tol, or a cycle that
+                          does not contract); converged is 0 then */
 } ht_solve_stats;
 
 /* ------------------------------------------------------------ general -- */
@@ -341,7 +345,9 @@ int ht_vcycle(ht_mesh* mesh, int level, int dtype, const ht_cycle_opts* opts,
  * once per cycle to read the residual norm.
  * Repeats the V-cycle of Section 6's solvers until the relative residual
  * ||b - A u|| / ||b|| falls below opts->rel_tol, or opts->max_cycles
- * cycles have run (HT_ERR_NOT_CONVERGED, u holds the last iterate).  u
+ * cycles have run, or three cycles in a row bring no new minimum of the
+ * residual (stats->stagnated; both HT_ERR_NOT_CONVERGED, u holds the last
+ * iterate).  u
  * updated in place, b read: n_slots(level) FP64 elements in device memory;
  * stats (host, may be NULL) receives the cycle count, final relative
  * residual, wall time and residual history. */
@@ -381,10 +387,10 @@ int ht_batch_query(const ht_batch* batch, int* n_problems, int64_t* n_dofs,
  * vectors in the layout of mesh p at its finest level (n_slots of
  * ht_mesh_query for that mesh and level); u[p] holds the initial iterate
  * and receives the solution.  Every problem runs V(nu1, nu2) cycles until
- * its own relative residual is <= rel_tol; its result is the iterate of
- * the cycle at which it converged (later cycles of the batch do not change
- * it), so it equals what ht_solve computes for that problem alone, up to
- * rounding.  stats: array of n, one per problem.  opts->precision:
+ * its own relative residual is <= rel_tol, or until it stagnates as in
+ * ht_solve (stats[p].stagnated); its result is the iterate of the cycle at
+ * which it stopped (later cycles of the batch do not change it), so it
+ * equals what ht_solve computes for that problem alone, up to rounding.  stats: array of n, one per problem.  opts->precision:
  * HT_PREC_F64 (FP64 V-cycles) or HT_PREC_MIXED (FP32-in-FP64 iterative
  * refinement as in ht_solve: FP32 correction cycles of all problems in one
  * batched V-cycle, FP64 residuals, norms and updates).  The Jacobi smoother

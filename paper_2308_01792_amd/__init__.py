@@ -325,9 +325,7 @@ class Mesh:
                                C.byref(st), _stream())
         if code != _lib.HT_ERR_NOT_CONVERGED or raise_on_fail:
             check(code)
-        return {"cycles": st.cycles, "converged": bool(st.converged),
-                "rel_res": st.rel_res, "seconds": st.seconds,
-                "history": list(st.res_history[:st.cycles + 1])}
+        return _stats_dict(st)
 
     def fmg(self, level: int, u, b, cycles=5, nu1=2, nu2=2, omega=2.0 / 3.0,
             coarse_level=2, want_residual=True, smoother=HT_SMOOTH_JACOBI,
@@ -393,6 +391,7 @@ class Mesh:
 
 def _stats_dict(st):
     return {"cycles": st.cycles, "converged": bool(st.converged),
+            "stagnated": bool(st.stagnated),
             "rel_res": st.rel_res, "seconds": st.seconds,
             "history": list(st.res_history[:st.cycles + 1])}
 

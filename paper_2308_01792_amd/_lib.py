@@ -47,7 +47,7 @@ class SolveOpts(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("converged", C.c_int),
                 ("rel_res", C.c_double), ("seconds", C.c_double),
-                ("res_history", C.c_double * 257)]
+                ("res_history", C.c_double * 257), ("stagnated", C.c_int)]
 
 
 # name -> (restype, argtypes); every exported symbol of include/hytet.h

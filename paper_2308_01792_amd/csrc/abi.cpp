@@ -1910,6 +1910,10 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
       first_sweep(s);
       HT_CHECK_HIP(hipStreamSynchronize(s));
     }
+    // stagnation: three cycles in a row without a new minimum of the residual
+    double best = rel;
+    int kbest = 0;
+    bool stagnated = false;
     while (rel > o->rel_tol && k < o->max_cycles && std::isfinite(rel)) {
       if (!fused) {
         if (o->use_graph) run_graph(h, key.str(), step, s);
@@ -1928,14 +1932,23 @@ int ht_solve(ht_mesh* h, int level, const ht_solve_opts* o, void* u,
       rel = h->m.h_scalar[0] * scale;
       ++k;
       st->res_history[k] = rel;
+      if (rel < best) {
+        best = rel;
+        kbest = k;
+      } else if (rel > o->rel_tol && k - kbest >= 3) {
+        stagnated = true;
+        break;
+      }
     }
     st->cycles = k;
     st->rel_res = rel;
     st->converged = rel <= o->rel_tol;
+    st->stagnated = stagnated;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (!st->converged)
-      throw Error{HT_ERR_NOT_CONVERGED, "relative residual " + std::to_string(rel) +
-                                            " after " + std::to_string(k) + " cycles"};
+      throw Error{HT_ERR_NOT_CONVERGED,
+                  std::string(stagnated ? "stagnated: " : "") + "relative residual " +
+                      std::to_string(rel) + " after " + std::to_string(k) + " cycles"};
   });
   return rc;
 }
@@ -2223,6 +2236,10 @@ int ht_batch_solve(ht_batch* B, const ht_solve_opts* o, void* const* u,
                                   hipMemcpyDeviceToDevice, s));
     };
     // a problem is frozen (copied out) at the first cycle that meets rel_tol
+    // ... or at the third cycle in a row without a new minimum of its
+    // residual (stagnation, as in ht_solve)
+    std::vector<double> best(P, HUGE_VAL);
+    std::vector<int> kbest(P, 0);
     auto record = [&](int k) {
       for (int p = 0; p < P; ++p) {
         if (done[p]) continue;
@@ -2230,7 +2247,15 @@ int ht_batch_solve(ht_batch* B, const ht_solve_opts* o, void* const* u,
         ps[p].res_history[k] = rel;
         ps[p].cycles = k;
         ps[p].rel_res = rel;
-        if (rel <= o->rel_tol || !std::isfinite(rel)) {
+        bool stop = rel <= o->rel_tol || !std::isfinite(rel);
+        if (rel < best[p]) {
+          best[p] = rel;
+          kbest[p] = k;
+        } else if (!stop && k - kbest[p] >= 3) {
+          ps[p].stagnated = 1;
+          stop = true;
+        }
+        if (stop) {
           ps[p].converged = rel <= o->rel_tol;
           done[p] = 1;
           --open;

@@ -219,3 +219,25 @@ def test_mixed_update_inside_the_last_sweep_matches_a_separate_update():
     assert s1["cycles"] == s2["cycles"] == 3
     assert np.allclose(s1["history"], s2["history"], rtol=1e-12, atol=0)
     assert rel_err(u1.cpu().numpy(), u2.cpu().numpy()) <= 1e-13
+
+
+def test_batch_problems_stop_when_their_residual_stagnates(setup):
+    """A tolerance below the FP64 rounding floor: every problem stops three
+    cycles after its residual's last new minimum (stagnated, not converged),
+    well before max_cycles, and keeps the iterate of that cycle."""
+    meshes, bs, batch = setup
+    us = [torch.zeros_like(b) for b in bs]
+    st = batch.solve(us, bs, rel_tol=1e-30, max_cycles=200, raise_on_fail=False)
+    for p, s in enumerate(st):
+        h = np.array(s["history"])
+        kbest = int(np.argmin(h))
+        assert s["stagnated"] and not s["converged"], p
+        assert s["cycles"] < 200 and s["cycles"] - kbest == 3, p
+        assert h[kbest] <= 1e-14 and (h[kbest + 1:] >= h[kbest]).all(), p
+    # the frozen iterate is the one whose residual was reported
+    for p in (0, len(bs) - 1):
+        m, lvl = meshes[p], PROBLEMS[p].level
+        r = torch.zeros_like(bs[p])
+        nr = m.residual(lvl, us[p], bs[p], r, want_norm=True)
+        nb = m.norm(lvl, bs[p])
+        assert abs(nr / nb - st[p]["rel_res"]) <= 1e-3 * st[p]["rel_res"], p

@@ -398,6 +398,34 @@ def test_solve_mixed_precision():
     assert err <= 1e-8
 
 
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_solve_stops_when_the_residual_stagnates(precision):
+    """A tolerance below the rounding floor of FP64: the solve stops three
+    cycles after the residual's last new minimum instead of running to
+    max_cycles, reports stagnated (not converged), and u is the iterate of
+    the last cycle, whose residual the stats report."""
+    P = pair("jittered_288", 4, 2)
+    S = P.S(4)
+    b = S.lumped_mass * fields.uniform_values(S.mesh.num_vertices, 5)
+    bg = P.to_gpu(4, b)
+    ug = torch.zeros_like(bg)
+    prec = ht.HT_PREC_F64 if precision == "f64" else ht.HT_PREC_MIXED
+    st = P.m.solve(4, ug, bg, prec, 1e-30, 200, raise_on_fail=False)
+    h = np.array(st["history"])
+    assert st["stagnated"] and not st["converged"]
+    assert st["cycles"] < 200 and len(h) == st["cycles"] + 1
+    kbest = int(np.argmin(h))
+    assert st["cycles"] - kbest == 3 and (h[kbest + 1:] >= h[kbest]).all()
+    assert h[kbest] <= 1e-14                      # reached the rounding floor
+    m = int(np.argmax(h <= 1e-13))                # contraction until near it
+    assert m > 5 and (h[1:m + 1] < h[:m]).all()
+    inner = ~S.dirichlet
+    r = S.residual(P.from_gpu(4, ug), b)
+    assert np.linalg.norm(r[inner]) <= 1e-13 * np.linalg.norm(b[inner])
+    with pytest.raises(ht._lib.HytetError, match="stagnated"):
+        P.m.solve(4, torch.zeros_like(bg), bg, prec, 1e-30, 200)
+
+
 @pytest.mark.parametrize("rows", [0, 4, 8, 16])
 @pytest.mark.parametrize("name,level", [("jittered_288", 4), ("ref_tet", 6),
                                         ("slab_3_11", 5), ("ref_tet", 7)])
