@@ -469,9 +469,10 @@ int ht_get_march_segment(const ht_mesh* mesh, int level, int dtype, int* planes)
  * keeps the fastest of each and returns the apply's choice in *rows (0 =
  * band kernel).  Only the cells present on the level take part (all of a
  * plain mesh; in a batch's union mesh, the problems whose finest level is at
- * least `level`).  With cache_path != NULL a text cache keyed by (gfx arch,
- * level, dtype, cells, cell stride) is read first and appended to after
- * tuning.  Captured graphs of the mesh are dropped (they hold the old
+ * least `level`).  With cache_path != NULL (or, when it is NULL, the path in
+ * the environment variable HT_TUNE_CACHE if set and not empty) a text cache
+ * keyed by (gfx arch, level, dtype, cells, cell stride) is read first and
+ * appended to after tuning; ht_batch_autotune reads the same variable.  Captured graphs of the mesh are dropped (they hold the old
  * shapes).  Synchronises. */
 int ht_autotune(ht_mesh* mesh, int level, int dtype, const char* cache_path,
                 int* rows, ht_stream stream);

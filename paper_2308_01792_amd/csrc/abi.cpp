@@ -2392,6 +2392,10 @@ static Range level_range(const Mesh& m, int level) {
 // Autotuning of one (level, dtype) over the cells present on the level.
 static void autotune_level(ht_mesh* h, int level, int dtype, const char* cache_path,
                            int* rows, hipStream_t s) {
+  if (!cache_path) {
+    const char* env = std::getenv("HT_TUNE_CACHE");
+    if (env && *env) cache_path = env;
+  }
   // cache: lines "<gfx arch> <level> <dtype> <cells> <stride> v3
   // <apply rows> <sweep rows> <sweep waves in i> <sweep segment>"
   hipDeviceProp_t prop;

@@ -483,6 +483,21 @@ def test_autotune_picks_a_valid_shape(tmp_path):
     assert open(cache).read().count("\n") == 1
 
 
+def test_autotune_cache_from_the_environment(tmp_path, monkeypatch):
+    """Without a cache path the autotuner uses HT_TUNE_CACHE: the first call
+    tunes and appends one line, a second mesh reads the shapes back."""
+    cache = tmp_path / "env_tune.txt"
+    monkeypatch.setenv("HT_TUNE_CACHE", str(cache))
+    P = pair("jittered_288", 4, 4)
+    rows = P.m.autotune(4, ht.HT_F32)
+    assert cache.read_text().count("\n") == 1
+    sweep = P.m.sweep_shape(4, ht.HT_F32)
+    m2 = ht.Mesh(*mesh_by_name("jittered_288"), 2, 4)
+    assert m2.autotune(4, ht.HT_F32) == rows
+    assert m2.sweep_shape(4, ht.HT_F32) == sweep
+    assert cache.read_text().count("\n") == 1
+
+
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_sweeps_do_not_depend_on_the_march_segment(dt):
     """Jacobi sweeps and the residual with every march segment length give
