@@ -190,8 +190,10 @@ static int64_t partials_needed(const ht_mesh* h, int level) {
   for (int J : kJ)
     for (bool in_i : {false, true})
       cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J, in_i, kSegs[0]).size());
-  const int64_t fp = n_tri(n - 2), total = m.n_faces * fp + m.n_edges * std::max(n - 1, 0) + m.n_verts;
-  const int64_t exch_blocks = (total + 255) / 256;
+  // exchange blocks (exch_args): per face, per edge, then the vertices
+  const int64_t exch_blocks = m.n_faces * ((n_tri(n - 2) + 255) / 256) +
+                              m.n_edges * ((std::max(n - 1, 0) + 255) / 256) +
+                              (m.n_verts + 255) / 256;
   const int64_t elem_blocks = m.nc * (int64_t)make_walk_tiles(n).size();
   return std::max(cell_blocks + exch_blocks, elem_blocks) + 512;
 }
@@ -217,10 +219,25 @@ void ensure_uploaded_h(ht_mesh* h) {
     dp[p].dim = (int8_t)P.dim;
     dp[p].boundary = P.boundary ? 1 : 0;
     dp[p].inv_diag_unit = P.boundary ? 0.0 : 1.0 / P.diag_unit;
+    // The exchange numbers a face's interior points with the face's second
+    // vertex as the fast coordinate.  Faces take their vertices in the order
+    // (other, fast, slow) of the first incident cell's storage: along S0 and
+    // S1 rows j is fast and k slow; along the M rows of the faces j = 0 and
+    // k = 0, i is fast.  That cell's copy is then read and written in
+    // contiguous runs.  All incidences follow the same vertex order.
+    int perm[3] = {0, 1, 2};
+    if (P.dim == 2 && !P.inc.empty()) {
+      const Incidence& I0 = P.inc[0];
+      const int q = 6 - I0.lv[0] - I0.lv[1] - I0.lv[2];  // vertex opposite the face
+      static const int order[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+      for (int mm = 0; mm < 3; ++mm)
+        for (int v = 0; v < 3; ++v)
+          if (I0.lv[v] == order[q][mm]) perm[mm] = v;
+    }
     for (const Incidence& I : P.inc) {
       DevInc d;
       d.cell = I.cell;
-      d.lv[0] = I.lv[0]; d.lv[1] = I.lv[1]; d.lv[2] = I.lv[2];
+      for (int mm = 0; mm < 3; ++mm) d.lv[mm] = I.lv[perm[mm]];
       d.cls = I.cls;
       di.push_back(d);
     }
@@ -466,6 +483,12 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
   a.face_end = a.n_faces * a.face_pts;
   a.edge_end = a.face_end + a.n_edges * std::max(n - 1, 0);
   a.total = a.edge_end + (R.v1 - R.v0);
+  a.bpf = (a.face_pts + 255) / 256;
+  a.bpe = (std::max(n - 1, 0) + 255) / 256;
+  a.fblk = a.n_faces * a.bpf;
+  a.eblk = a.n_edges * a.bpe;
+  a.nverts = R.v1 - R.v0;
+  a.nblocks = a.fblk + a.eblk + (a.nverts + 255) / 256;
   a.omega = omega;
   a.nscale = (double)n;
   return a;
@@ -520,7 +543,7 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
       check_launch();
     }
     if (op != OP_APPLY && want_norm) {
-      const int64_t cnt = kBandComputeWaves * ba.nblocks + (ea.total + 255) / 256;
+      const int64_t cnt = kBandComputeWaves * ba.nblocks + ea.nblocks;
       Prof p(h, "norm_sum", s);
       launch_sum_partials(partials, cnt, norm_dst, true, s);
       check_launch();
@@ -551,7 +574,7 @@ static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,
   }
   if ((op == OP_RESID || op == OP_RESID32 || op == OP_RESID32X || op == OP_JACOBI) &&
       want_norm) {
-    const int64_t cnt = kCellWaves * ca.nblocks + (ea.total + 255) / 256;
+    const int64_t cnt = kCellWaves * ca.nblocks + ea.nblocks;
     Prof p(h, "norm_sum", s);
     launch_sum_partials(partials, cnt, norm_dst, true, s);
     check_launch();
@@ -563,9 +586,9 @@ static int64_t pass_partials(ht_mesh* h, int level, int dtype, int op, const Ran
   const ExchArgs ea = exch_args(h, level, nullptr, nullptr, nullptr, 0.0, nullptr, R);
   if (sh.J == 0 && band_op(op))
     return kBandComputeWaves * band_args(h, level, dtype, nullptr, nullptr, R).nblocks +
-           (ea.total + 255) / 256;
+           ea.nblocks;
   const CellArgs ca = cell_args(h, level, dtype, sh, nullptr, nullptr, nullptr, 0.0, R);
-  return kCellWaves * ca.nblocks + (ea.total + 255) / 256;
+  return kCellWaves * ca.nblocks + ea.nblocks;
 }
 
 static void op_pass(ht_mesh* h, int level, int dtype, int op, const void* x,

@@ -393,50 +393,61 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell(CellArgs a) {
 }
 
 // ------------------------------------------------ ghost-exchange kernel --
-// Decode p in [0, N_tri(m)) into (a, b) with rows b of length m - b.
-__device__ __forceinline__ void tri_decode(int64_t p, int m, int& a, int& b) {
-  const double q = 2.0 * m + 1.0;
-  int bb = (int)floor((q - sqrt(q * q - 8.0 * (double)p)) * 0.5);
-  auto start = [&](int r) -> int64_t { return (int64_t)r * m - (int64_t)r * (r - 1) / 2; };
-  if (bb < 0) bb = 0;
-  while (bb > 0 && start(bb) > p) --bb;
-  while (bb + 1 < m && start(bb + 1) <= p) ++bb;
+// Decode p in [0, N_tri(m)) into (a, b) with rows b of length m - b, for
+// m <= 2046: row b starts at b m - b (b - 1) / 2; the FP32 root of the
+// quadratic is exact to one row (all operands are integers below 2^24), and
+// one comparison each way corrects it.
+__device__ __forceinline__ void tri_decode(int p, int m, int& a, int& b) {
+  const float q = 2.0f * (float)m + 1.0f;
+  int bb = (int)((q - __builtin_sqrtf(q * q - 8.0f * (float)p)) * 0.5f);
+  bb = bb < 0 ? 0 : (bb > m - 1 ? m - 1 : bb);
+  auto start = [&](int r) { return r * m - ((r * (r - 1)) >> 1); };
+  if (start(bb) > p) --bb;
+  else if (bb + 1 < m && start(bb + 1) <= p) ++bb;
   b = bb;
-  a = (int)(p - start(bb));
+  a = p - start(bb);
 }
 
-
-// One thread per micro-vertex shared by several cells (face interiors, then
-// edge interiors, then vertices).  Sums the partial rows of all incident
-// cells in cell order, applies the epilogue of OP and writes every copy.
+// One thread per micro-vertex shared by several cells: blocks of one face's
+// interior points, then of one edge's, then of the vertices.  Sums the
+// partial rows of all incident cells in cell order, applies the epilogue of
+// OP and writes every copy.
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Lay L{a.n, a.stride, a.off_s0, a.off_s1};
   const int n = L.n;
+  const int tid = (int)threadIdx.x;
+  // the block's primitive: uniform, so the divisions are scalar
+  const int64_t blk = blockIdx.x;
+  int64_t prim;
+  bool valid;
+  int gw[3] = {0, 0, 0};
+  if (blk < a.fblk) {
+    const int64_t fl = blk / a.bpf;  // face within the range
+    const int p = (int)(blk - fl * a.bpf) * 256 + tid;
+    prim = a.prim_f0 + fl;
+    valid = p < a.face_pts;
+    int aa = 0, bb = 0;
+    tri_decode(valid ? p : 0, n - 2, aa, bb);
+    gw[1] = aa + 1;
+    gw[2] = bb + 1;
+    gw[0] = n - gw[1] - gw[2];
+  } else if (blk < a.fblk + a.eblk) {
+    const int64_t eb = blk - a.fblk;
+    const int64_t el = eb / a.bpe;
+    const int s = (int)(eb - el * a.bpe) * 256 + tid;
+    prim = a.prim_e0 + el;
+    valid = s < n - 1;
+    gw[1] = s + 1;
+    gw[0] = n - gw[1];
+  } else {
+    const int64_t v = (blk - a.fblk - a.eblk) * 256 + tid;
+    prim = a.prim_v0 + v;
+    valid = v < a.nverts;
+    gw[0] = n;
+  }
   double nsq = 0.0;
-  if (t < a.total) {
-    int64_t prim;
-    int gw[3] = {0, 0, 0};
-    if (t < a.face_end) {
-      const int64_t fp = a.face_pts;
-      const int64_t fl = t / fp;  // face within the range
-      prim = a.prim_f0 + fl;
-      int aa, bb;
-      tri_decode(t - fl * fp, n - 2, aa, bb);
-      gw[1] = aa + 1;
-      gw[2] = bb + 1;
-      gw[0] = n - gw[1] - gw[2];
-    } else if (t < a.edge_end) {
-      const int64_t s = t - a.face_end;
-      const int64_t ep = n - 1;
-      prim = a.prim_e0 + s / ep;
-      gw[1] = (int)(s % ep) + 1;
-      gw[0] = n - gw[1];
-    } else {
-      prim = a.prim_v0 + (t - a.edge_end);
-      gw[0] = n;
-    }
+  if (valid) {
     const DevPrim P = a.prim[prim];
     const int cnt = P.inc_count;
     // local index of this point in the q-th incident cell
@@ -455,22 +466,20 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
       return (int64_t)I.cell * L.stride + slot_of(L, i, j, k);
     };
     T* y = (T*)a.y;
+    // slots of the first two copies (all of a face's) formed once
     const int64_t s0 = slot_q(0);
+    const int64_t s1 = cnt > 1 ? slot_q(1) : s0;
+    auto slot_c = [&](int q) -> int64_t { return q == 0 ? s0 : (q == 1 ? s1 : slot_q(q)); };
     if (OP == OP_SYNC) {
       const T v = y[s0];
-      for (int q = 1; q < cnt; ++q) y[slot_q(q)] = v;
+      for (int q = 1; q < cnt; ++q) y[slot_c(q)] = v;
     } else if (OP == OP_FILL) {
       if (P.boundary)
-        for (int q = 0; q < cnt; ++q) y[slot_q(q)] = (T)a.fill;
+        for (int q = 0; q < cnt; ++q) y[slot_c(q)] = (T)a.fill;
     } else {
       // partial rows of the incident cells, summed in cell order
       T sum = (T)0;
-      for (int q = 0; q < cnt; ++q) {
-        int i, j, k;
-        const DevInc I = local_q(q, i, j, k);
-        const int64_t cb = (int64_t)I.cell * L.stride;
-        sum += y[cb + slot_of(L, i, j, k)];
-      }
+      for (int q = 0; q < cnt; ++q) sum += y[slot_c(q)];
       T val;
       if (P.boundary) {
         val = (OP == OP_JACOBI || OP == OP_JACOBIADD || OP == OP_CHEB) ? ((const T*)a.u)[s0]
@@ -491,14 +500,14 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
         const T dn = fma((T)a.c1, a.c1 != 0.0 ? d[s0] : (T)0, (T)a.c2 * (invd * r));
         val = ((const T*)a.u)[s0] + dn;
         d[s0] = dn;
-        for (int q = 1; q < cnt; ++q) d[slot_q(q)] = dn;
+        for (int q = 1; q < cnt; ++q) d[slot_c(q)] = dn;
       } else {
         val = sum;
       }
       if (OP == OP_RESID32 || OP == OP_RESID32X) {
         float* y32 = (float*)a.y32;
         y32[s0] = (float)val;
-        for (int q = 1; q < cnt; ++q) y32[slot_q(q)] = (float)val;
+        for (int q = 1; q < cnt; ++q) y32[slot_c(q)] = (float)val;
         if (OP == OP_RESID32X) {
           // first zero-guess sweep of the next correction (0 on the
           // Dirichlet boundary, where val is 0)
@@ -506,15 +515,15 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
           const float e = (float)(a.omega * a.nscale * P.inv_diag_unit) * (float)val;
           float* ef = (float*)a.efirst;
           ef[s0] = e;
-          for (int q = 1; q < cnt; ++q) ef[slot_q(q)] = e;
+          for (int q = 1; q < cnt; ++q) ef[slot_c(q)] = e;
         }
       } else if (OP == OP_JACOBIADD) {
         double* ua = a.uadd;
         ua[s0] += (double)val;
-        for (int q = 1; q < cnt; ++q) ua[slot_q(q)] += (double)val;
+        for (int q = 1; q < cnt; ++q) ua[slot_c(q)] += (double)val;
       } else {
         y[s0] = val;
-        for (int q = 1; q < cnt; ++q) y[slot_q(q)] = val;
+        for (int q = 1; q < cnt; ++q) y[slot_c(q)] = val;
       }
     }
   }
@@ -637,7 +646,7 @@ void launch_cell(int dtype, int op, int J, const CellArgs& a, hipStream_t s) {
 
 template <typename T>
 static void launch_exchange_t(int op, const ExchArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.total + 255) / 256));
+  const dim3 grid((unsigned)a.nblocks);
   switch (op) {
     case OP_APPLY: hipLaunchKernelGGL((k_exchange<T, OP_APPLY>), grid, dim3(256), 0, s, a); break;
     case OP_RESID: hipLaunchKernelGGL((k_exchange<T, OP_RESID>), grid, dim3(256), 0, s, a); break;

@@ -82,7 +82,10 @@ struct ExchArgs {
   int64_t n_faces, n_edges;             // faces and edges of the range
   int64_t prim_f0, prim_e0, prim_v0;    // primitive index of the range's
                                         // first face, edge and vertex
-  int64_t face_pts, face_end, edge_end, total;
+  int64_t face_pts, face_end, edge_end, total;  // points: total = all shared
+  // blocks of 256 threads: bpf per face (face interiors first), bpe per
+  // edge, then the vertices; nblocks in all (one norm partial per block)
+  int64_t bpf, bpe, fblk, eblk, nverts, nblocks;
   double omega, nscale, fill;
 };
 
