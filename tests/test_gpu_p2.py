@@ -123,8 +123,14 @@ def _points(n):
                 (c, 1, 1, n - 3), (c, n - 3, 1, 1), (c, 125, 126, n - 252),
                 (c, 0, 5, n - 9), (c, 5, 0, n - 9), (c, n - 14, 5, 9),
                 (c, 0, 0, n // 2), (c, 3, 0, 0), (c, 127, 3, 2)]
+    # face points at the borders of the face kernel's tiles (8 planes x 128
+    # rows): rows 127 / 128 / 129 and planes 7 / 8 / 9, both faces
+    for (j, k) in ((127, 7), (128, 8), (129, 9), (1, 8), (126, 15), (128, 16),
+                   (n - 18, 16), (3, n - 5)):
+        if j + k <= n - 1:
+            pts += [(97, 0, j, k), (97, n - j - k, j, k)]
     rng = np.random.default_rng(43)
-    while len(pts) < 60:
+    while len(pts) < 76:
         i, j, k = rng.integers(0, n + 1, size=3)
         if i + j + k <= n:
             pts.append((int(rng.integers(0, 288)), int(i), int(j), int(k)))
