@@ -176,10 +176,15 @@ static std::vector<int2> make_tiles(int n, int J, bool in_i, int seg = 0) {
   return t;
 }
 
+// Walk tiles of one cell: (i0, j0 | k0 << 16), 64 i x 8 rows, planes k0 ..
+// k0 + kWalkSeg - 1 up to n - i0 - j0; consecutive tiles are the segments of
+// one column.
 static std::vector<int2> make_walk_tiles(int n) {
   std::vector<int2> t;
   for (int tj = 0; 8 * tj <= n; ++tj)
-    for (int ti = 0; 64 * ti + 8 * tj <= n; ++ti) t.push_back(make_int2(64 * ti, 8 * tj));
+    for (int ti = 0; 64 * ti + 8 * tj <= n; ++ti)
+      for (int k0 = 0; k0 <= n - 64 * ti - 8 * tj; k0 += kWalkSeg)
+        t.push_back(make_int2(64 * ti, (8 * tj) | (k0 << 16)));
   return t;
 }
 

@@ -101,6 +101,10 @@ struct XferArgs {
   int64_t stride_c, off_s0_c, off_s1_c;
 };
 
+// Planes per walk tile of the transfer and elementwise kernels (even, so that
+// the prolongation's plane pairs start on an even plane).
+enum { kWalkSeg = 16 };
+
 struct ElemArgs {
   void* out;
   const void* in0;

@@ -12,16 +12,18 @@ namespace ht {
 // --------------------------------------------------------- tile walker --
 // The transfer and elementwise kernels visit the closure points of one
 // (cell, walk tile) per wave: lanes are 64 consecutive i = i0 + lane, rows
-// j0 .. j0 + kWalkRows - 1, planes k = 0 .. n - i0 - j0.  A workgroup holds
-// kWalkWaves waves on consecutive walk tiles, so that enough waves are
-// resident per CU for these streaming kernels.
+// j0 .. j0 + kWalkRows - 1, planes k0 .. k0 + kWalkSeg - 1 (up to
+// n - i0 - j0; a column of tiles is cut into segments so that no wave walks
+// far longer than the others).  A workgroup holds kWalkWaves waves on
+// consecutive walk tiles, so that enough waves are resident per CU for these
+// streaming kernels.
 enum { kWalkRows = 8, kWalkWaves = 4 };
 
 // (block, wave) -> (cell, tile).  Consecutive blocks go to different XCDs;
 // each XCD gets one contiguous run of tiles, as in the stencil kernel.
 __device__ __forceinline__ bool walk_block(int64_t nblocks, int64_t ntiles,
                                            const int2* tiles, int wave,
-                                           int64_t& cell, int& i0, int& j0,
+                                           int64_t& cell, int& i0, int& j0, int& k0,
                                            int64_t& w) {
   const int64_t groups = (nblocks + kWalkWaves - 1) / kWalkWaves;
   const int64_t chunk = (groups + 7) / 8;
@@ -30,7 +32,8 @@ __device__ __forceinline__ bool walk_block(int64_t nblocks, int64_t ntiles,
   cell = w / ntiles;
   const int2 t = tiles[w % ntiles];
   i0 = t.x;
-  j0 = t.y;
+  j0 = t.y & 0xffff;
+  k0 = t.y >> 16;
   return true;
 }
 
@@ -66,9 +69,9 @@ constexpr int kParDj[8] = {0, 0, 1, 1, 0, 0, -1, -1};
 template <typename T>
 __global__ __launch_bounds__(64 * kWalkWaves) void k_prolong(XferArgs a) {
   int64_t cell, w;
-  int i0, j0;
+  int i0, j0, k0;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if (!walk_block(a.nblocks, a.ntiles, a.tiles, wave, cell, i0, j0, w)) return;
+  if (!walk_block(a.nblocks, a.ntiles, a.tiles, wave, cell, i0, j0, k0, w)) return;
   const int lane = threadIdx.x & 63;
   const uint8_t fl = lane < 16 ? a.cls[cell * 16 + lane].flags : 0;
   const unsigned dmask = (unsigned)__ballot((fl & kClsDirichlet) != 0) & 0xffffu;
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_prolong(XferArgs a) {
   const int n = Lf.n, w1 = n - 1, i = i0 + lane;
   const bool odd = (lane & 1) != 0;
   const int jc0 = j0 >> 1;
-  const int kmax = n - i0 - j0;
+  const int kmax = min(n - i0 - j0, k0 + kWalkSeg - 1);  // k0 is even
 
   // Fine plane k (parity PK); R[p][s] is coarse row jc0 + s of plane
   // k / 2 + p.  All loads of the plane's rows first, then the updates.
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_prolong(XferArgs a) {
     }
   };
 
-  for (int k = 0; k <= kmax; k += 2) {
+  for (int k = k0; k <= kmax; k += 2) {
     CRow R[2][5];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
@@ -154,10 +157,10 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_prolong(XferArgs a) {
 template <typename T, int EOP>
 __global__ __launch_bounds__(64 * kWalkWaves) void k_elem(ElemArgs a) {
   int64_t cell, w;
-  int i0, j0;
+  int i0, j0, k0;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
-  const bool live = walk_block(a.nblocks, a.ntiles, a.tiles, wave, cell, i0, j0, w);
+  const bool live = walk_block(a.nblocks, a.ntiles, a.tiles, wave, cell, i0, j0, k0, w);
   // class table of the wave's cell; every wave reaches the barrier
   __shared__ ClassInfo cis[kWalkWaves][16];
   // zero-guess factor per class: omega / diagonal, 0 at Dirichlet points
@@ -179,9 +182,9 @@ __global__ __launch_bounds__(64 * kWalkWaves) void k_elem(ElemArgs a) {
       make_rsrc(a.in1 ? (const T*)a.in1 + cb : (const T*)a.out + cb, bytes);
   const __amdgpu_buffer_rsrc_t ro = make_rsrc((T*)a.out + cb, bytes);
   const int n = L.n, w1 = n - 1, i = i0 + lane;
-  const int kmax = n - i0 - j0;
+  const int kmax = min(n - i0 - j0, k0 + kWalkSeg - 1);
   double acc = 0.0;
-  for (int k = 0; k <= kmax; ++k) {
+  for (int k = k0; k <= kmax; ++k) {
     unsigned off[kWalkRows];
     int cl[kWalkRows], elr[kWalkRows];
     int mb = (int)(tet32(w1) - tet32(w1 - k)) - 1 + j0 * (w1 - k) - j0 * (j0 - 1) / 2;
