@@ -628,11 +628,14 @@ static const void* vcoef_couplings(ht_mesh* h, int level, int dtype) {
 
 // Unsegmented tiles for the variable-coefficient kernel, cached under -J so
 // that they never mix with the stencil kernel's segmented tiles.
+// Planes per march segment of the variable-coefficient kernel: a column of
+// tiles near i0 = j0 = 0 spans all n + 1 planes, one near the apex a few.
+static const int kVcoefSeg = 32;
 static const std::pair<int2*, int64_t>& tiles_of(ht_mesh* h, int level, int J) {
-  auto it = h->tiles.find({level, -J, false, 0});
+  auto it = h->tiles.find({level, -J, false, kVcoefSeg});
   if (it == h->tiles.end()) {
-    auto t = make_tiles(1 << level, J, false);
-    it = h->tiles.emplace(std::make_tuple(level, -J, false, 0),
+    auto t = make_tiles(1 << level, J, false, kVcoefSeg);
+    it = h->tiles.emplace(std::make_tuple(level, -J, false, kVcoefSeg),
                           std::make_pair(upload(t), (int64_t)t.size())).first;
   }
   return it->second;
@@ -655,6 +658,7 @@ static void vcoef_pass(ht_mesh* h, int level, int dtype, int mode,
   a.nblocks = m.nc * t.second;
   a.stride = L.stride; a.off_s0 = L.off_s0; a.off_s1 = L.off_s1;
   a.n = L.n;
+  a.kseg = kVcoefSeg;
   {
     Prof p(h, mode == VC_APPLY ? "cell_divkgrad" : mode == VC_STORED ? "cell_stored" : "assemble", s);
     launch_vcell(dtype, mode, kVcoefJ, a, s);

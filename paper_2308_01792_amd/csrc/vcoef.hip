@@ -75,7 +75,7 @@ __device__ __forceinline__ void gather15(T (&v)[15], const T (&pm)[J + 2],
 }  // namespace
 
 template <typename T, int MODE, int J>
-__global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
+__global__ __launch_bounds__(64 * kCellWaves) __attribute__((amdgpu_waves_per_eu(2))) void k_vcell(VCellArgs a) {
   constexpr bool LOAD_X = MODE != VC_ASSEMBLE;
   constexpr bool LOAD_K = MODE != VC_STORED;
   __shared__ T ctab[kVcoefPerCell];
@@ -88,7 +88,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
   const int2 tile = a.tiles[wb % a.ntiles];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int i0 = tile.x, j0 = tile.y + wave * J;
+  // tile (i0, j0 | k0 << 16): the march covers planes k0 .. k0 + kseg - 1
+  const int i0 = tile.x, j0 = (tile.y & 0xffff) + wave * J, k0 = tile.y >> 16;
   const int n = a.n;
   const int64_t bytes = a.stride * (int64_t)sizeof(T);
   const __amdgpu_buffer_rsrc_t rx = make_rsrc((const T*)a.x + cell * a.stride, bytes);
@@ -111,7 +112,12 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
   // Scalar cursor over the planes (closure layout of index.hpp): element
   // bases of plane ck in the main block (minus one), in S0 and in S1.
   const int wm = n - 1;
-  int ck = 0, cmb = -1, csa = (int)a.off_s0, csb = (int)a.off_s1;
+  // (started at plane k0 - 1 from the closed forms of the plane sizes; for
+  // k0 = 0 the plane -1 yields no offset and its advance lands on plane 0)
+  int ck = k0 - 1;
+  int cmb = -1 + tet32(wm) - tet32(wm - ck),
+      csa = (int)a.off_s0 + tri32(n + 1) - tri32(n + 1 - ck),
+      csb = (int)a.off_s1 + tri32(n) - tri32(n - ck);
   // Byte offsets of this lane's point in rows j0-1 .. j0+J of plane ck
   // (HT_OOB outside the closure), then move the cursor to the next plane.
   auto plane_offsets = [&](unsigned (&o)[J + 2]) {
@@ -123,7 +129,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
     for (int r = 0; r < J + 2; ++r) {
       const int j = jf + r;
       const int e = n - j - kk;
-      const bool row_ok = j >= 0 && e >= 0;
+      const bool row_ok = j >= 0 && e >= 0 && kk >= 0;
       int el = (i == e) ? sb : mb + i;
       el = is0 ? sa : el;
       o[r] = (row_ok && (unsigned)i <= (unsigned)e) ? (unsigned)el * (unsigned)sizeof(T)
@@ -230,13 +236,19 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
   T QA[J + 2], QB[J + 2], QC[J + 2], QD[J + 2];
   unsigned OA[J + 2], OB[J + 2], OC[J + 2], OD[J + 2];
   T WA[J][15], WB[J][15];
-  plane_offsets(OB);
-  plane_offsets(OC);
+  // planes k0 - 1 (all offsets out of range below the cell), k0, k0 + 1
+  plane_offsets(OA);
 #pragma unroll
   for (int r = 0; r < J + 2; ++r) {
     PA[r] = (T)0;
     QA[r] = (T)0;
-    OA[r] = HT_OOB;
+    if (LOAD_X) bload(PA[r], rx, OA[r]);
+    if (LOAD_K) bload(QA[r], rk, OA[r]);
+  }
+  plane_offsets(OB);
+  plane_offsets(OC);
+#pragma unroll
+  for (int r = 0; r < J + 2; ++r) {
     if (LOAD_X) {
       bload(PB[r], rx, OB[r]);
       bload(PC[r], rx, OC[r]);
@@ -252,8 +264,9 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_vcell(VCellArgs a) {
 #pragma unroll
       for (int d = 0; d < 15; ++d) bload(WA[r][d], rw, OB[r + 1] + (unsigned)d * wstep);
   }
-  const int kmax = n - i0 - j0;
-  for (int k = 0; k <= kmax; k += 4) {
+  const int kcol = n - i0 - j0;
+  const int kmax = kcol < k0 + a.kseg - 1 ? kcol : k0 + a.kseg - 1;
+  for (int k = k0; k <= kmax; k += 4) {
     step(k, PA, PB, PC, PD, QA, QB, QC, QD, OB, OC, OD, WA, WB);
     if (k + 1 > kmax) break;
     step(k + 1, PB, PC, PD, PA, QB, QC, QD, QA, OC, OD, OA, WB, WA);

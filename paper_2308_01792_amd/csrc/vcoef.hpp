@@ -14,10 +14,11 @@ struct VCellArgs {
   void* y;              // output: full rows inside, partial rows on the surface
   const void* kc;       // [nc][36] level-scaled couplings (6 shapes x 6 edges)
   void* w;              // stored rows [nc][15][stride] (assemble / stored apply)
-  const int2* tiles;    // (i0, j0) of the non-empty tiles of one cell
+  const int2* tiles;    // (i0, j0 | k0 << 16) march segments of one cell
   int64_t ntiles, nblocks;
   int64_t stride, off_s0, off_s1;
   int n;
+  int kseg;             // planes per march segment (a multiple of 4)
 };
 
 // Couplings per cell: shape t, edge p (vertex pairs 01 02 03 12 13 23).
