@@ -196,7 +196,7 @@ static int64_t partials_needed(const ht_mesh* h, int level) {
     for (bool in_i : {false, true})
       cell_blocks = std::max<int64_t>(cell_blocks, kCellWaves * m.nc * (int64_t)make_tiles(n, J, in_i, kSegs[0]).size());
   // exchange blocks (exch_args): per face, per edge, then the vertices
-  const int64_t exch_blocks = m.n_faces * ((n_tri(n - 2) + 255) / 256) +
+  const int64_t exch_blocks = m.n_faces * ((n_tri(n - 2) + 256 * kExchFacePts - 1) / (256 * kExchFacePts)) +
                               m.n_edges * ((std::max(n - 1, 0) + 255) / 256) +
                               (m.n_verts + 255) / 256;
   const int64_t elem_blocks = m.nc * (int64_t)make_walk_tiles(n).size();
@@ -488,7 +488,7 @@ static ExchArgs exch_args(ht_mesh* h, int level, void* y, const void* u,
   a.face_end = a.n_faces * a.face_pts;
   a.edge_end = a.face_end + a.n_edges * std::max(n - 1, 0);
   a.total = a.edge_end + (R.v1 - R.v0);
-  a.bpf = (a.face_pts + 255) / 256;
+  a.bpf = (a.face_pts + 256 * kExchFacePts - 1) / (256 * kExchFacePts);
   a.bpe = (std::max(n - 1, 0) + 255) / 256;
   a.fblk = a.n_faces * a.bpf;
   a.eblk = a.n_edges * a.bpe;

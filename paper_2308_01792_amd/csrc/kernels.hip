@@ -408,10 +408,123 @@ __device__ __forceinline__ void tri_decode(int p, int m, int& a, int& b) {
   a = p - start(bb);
 }
 
+// Interior points of one face (one or two copies), kExchFacePts per thread:
+// the points chunk * 256 kExchFacePts + 256 u + thread.  All their loads are
+// issued before any store, so that one thread has several independent loads
+// in flight (the per-point chain of loads is what bounds the exchange).
+// Same arithmetic as the generic path below; returns the thread's |r|^2.
+template <typename T, int OP>
+__device__ __forceinline__ double exch_face(const ExchArgs& a, const Lay& L, int64_t fl,
+                                            int chunk, int tid) {
+  constexpr int U = kExchFacePts;
+  constexpr bool NEED_B = OP == OP_RESID || OP == OP_RESID32 || OP == OP_RESID32X ||
+                          OP == OP_JACOBI || OP == OP_JACOBIADD || OP == OP_CHEB;
+  constexpr bool NEED_U = OP == OP_JACOBI || OP == OP_JACOBIADD || OP == OP_CHEB;
+  const int n = L.n;
+  const DevPrim P = a.prim[a.prim_f0 + fl];
+  const int cnt = P.inc_count;  // 2, or 1 on the domain boundary
+  const DevInc I0 = a.inc[P.inc_begin];
+  const DevInc I1 = a.inc[P.inc_begin + (cnt > 1 ? 1 : 0)];
+  auto slot = [&](const DevInc& I, const int (&gw)[3]) -> int64_t {
+    int w[4] = {0, 0, 0, 0};
+    w[I.lv[0]] = gw[0];
+    w[I.lv[1]] = gw[1];
+    w[I.lv[2]] = gw[2];
+    return (int64_t)I.cell * L.stride + slot_of(L, w[1], w[2], w[3]);
+  };
+  T* y = (T*)a.y;
+  bool ok[U];
+  int64_t s0[U], s1[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = chunk * (256 * U) + 256 * u + tid;
+    ok[u] = p < a.face_pts;
+    int aa = 0, bb = 0;
+    tri_decode(ok[u] ? p : 0, n - 2, aa, bb);
+    const int gw[3] = {n - aa - bb - 2, aa + 1, bb + 1};
+    s0[u] = slot(I0, gw);
+    s1[u] = cnt > 1 ? slot(I1, gw) : s0[u];
+  }
+  // loads: the copies' values (partial rows, or the value to copy), b, u, d
+  T y0[U], y1[U], bv[U], uv[U], dv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    y0[u] = y1[u] = bv[u] = uv[u] = dv[u] = (T)0;
+    if (!ok[u]) continue;
+    if (OP != OP_FILL) y0[u] = y[s0[u]];
+    if (OP != OP_SYNC && OP != OP_FILL && cnt > 1) y1[u] = y[s1[u]];
+    if (NEED_B) bv[u] = ((const T*)a.b)[s0[u]];
+    if (NEED_U) uv[u] = ((const T*)a.u)[s0[u]];
+    if (OP == OP_CHEB && a.c1 != 0.0) dv[u] = ((const T*)a.d)[s0[u]];
+  }
+  double nsq = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (!ok[u]) continue;
+    if (OP == OP_SYNC) {
+      if (cnt > 1) y[s1[u]] = y0[u];
+      continue;
+    }
+    if (OP == OP_FILL) {
+      if (P.boundary) {
+        y[s0[u]] = (T)a.fill;
+        if (cnt > 1) y[s1[u]] = (T)a.fill;
+      }
+      continue;
+    }
+    // partial rows of the incident cells, summed in cell order
+    T sum = (T)0;
+    sum += y0[u];
+    if (cnt > 1) sum += y1[u];
+    T val;
+    if (P.boundary) {
+      val = NEED_U ? uv[u] : (T)0;
+    } else if (OP == OP_RESID || OP == OP_RESID32 || OP == OP_RESID32X) {
+      val = bv[u] - sum;
+      nsq += (double)val * (double)val;
+    } else if (OP == OP_JACOBI || OP == OP_JACOBIADD) {
+      const T invd = (T)(a.nscale * P.inv_diag_unit);
+      const T r = bv[u] - sum;
+      nsq += (double)r * (double)r;
+      val = uv[u] + (T)a.omega * invd * r;
+    } else if (OP == OP_CHEB) {
+      const T invd = (T)(a.nscale * P.inv_diag_unit);
+      const T r = bv[u] - sum;
+      nsq += (double)r * (double)r;
+      T* d = (T*)a.d;
+      const T dn = fma((T)a.c1, a.c1 != 0.0 ? dv[u] : (T)0, (T)a.c2 * (invd * r));
+      val = uv[u] + dn;
+      d[s0[u]] = dn;
+      if (cnt > 1) d[s1[u]] = dn;
+    } else {
+      val = sum;
+    }
+    if (OP == OP_RESID32 || OP == OP_RESID32X) {
+      float* y32 = (float*)a.y32;
+      y32[s0[u]] = (float)val;
+      if (cnt > 1) y32[s1[u]] = (float)val;
+      if (OP == OP_RESID32X) {
+        const float e = (float)(a.omega * a.nscale * P.inv_diag_unit) * (float)val;
+        float* ef = (float*)a.efirst;
+        ef[s0[u]] = e;
+        if (cnt > 1) ef[s1[u]] = e;
+      }
+    } else if (OP == OP_JACOBIADD) {
+      double* ua = a.uadd;
+      ua[s0[u]] += (double)val;
+      if (cnt > 1) ua[s1[u]] += (double)val;
+    } else {
+      y[s0[u]] = val;
+      if (cnt > 1) y[s1[u]] = val;
+    }
+  }
+  return nsq;
+}
+
 // One thread per micro-vertex shared by several cells: blocks of one face's
-// interior points, then of one edge's, then of the vertices.  Sums the
-// partial rows of all incident cells in cell order, applies the epilogue of
-// OP and writes every copy.
+// interior points (kExchFacePts per thread), then of one edge's, then of the
+// vertices.  Sums the partial rows of all incident cells in cell order,
+// applies the epilogue of OP and writes every copy.
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
   const Lay L{a.n, a.stride, a.off_s0, a.off_s1};
@@ -419,19 +532,13 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
   const int tid = (int)threadIdx.x;
   // the block's primitive: uniform, so the divisions are scalar
   const int64_t blk = blockIdx.x;
-  int64_t prim;
-  bool valid;
+  int64_t prim = 0;
+  bool valid = false;
   int gw[3] = {0, 0, 0};
+  double nsq = 0.0;
   if (blk < a.fblk) {
     const int64_t fl = blk / a.bpf;  // face within the range
-    const int p = (int)(blk - fl * a.bpf) * 256 + tid;
-    prim = a.prim_f0 + fl;
-    valid = p < a.face_pts;
-    int aa = 0, bb = 0;
-    tri_decode(valid ? p : 0, n - 2, aa, bb);
-    gw[1] = aa + 1;
-    gw[2] = bb + 1;
-    gw[0] = n - gw[1] - gw[2];
+    nsq = exch_face<T, OP>(a, L, fl, (int)(blk - fl * a.bpf), tid);
   } else if (blk < a.fblk + a.eblk) {
     const int64_t eb = blk - a.fblk;
     const int64_t el = eb / a.bpe;
@@ -446,7 +553,6 @@ __global__ __launch_bounds__(256) void k_exchange(ExchArgs a) {
     valid = v < a.nverts;
     gw[0] = n;
   }
-  double nsq = 0.0;
   if (valid) {
     const DevPrim P = a.prim[prim];
     const int cnt = P.inc_count;

@@ -83,8 +83,9 @@ struct ExchArgs {
   int64_t prim_f0, prim_e0, prim_v0;    // primitive index of the range's
                                         // first face, edge and vertex
   int64_t face_pts, face_end, edge_end, total;  // points: total = all shared
-  // blocks of 256 threads: bpf per face (face interiors first), bpe per
-  // edge, then the vertices; nblocks in all (one norm partial per block)
+  // blocks of 256 threads: bpf per face (face interiors first, kExchFacePts
+  // points per thread), bpe per edge, then the vertices; nblocks in all (one
+  // norm partial per block)
   int64_t bpf, bpe, fblk, eblk, nverts, nblocks;
   double omega, nscale, fill;
 };
@@ -104,6 +105,8 @@ struct XferArgs {
 // Planes per walk tile of the transfer and elementwise kernels (even, so that
 // the prolongation's plane pairs start on an even plane).
 enum { kWalkSeg = 16 };
+// Face points per thread of the exchange.
+enum { kExchFacePts = 4 };
 
 struct ElemArgs {
   void* out;
